@@ -1,0 +1,152 @@
+/*
+ * bk.h -- C ABI of the MI355X bispectrum-multipole estimator.
+ *
+ * Computes the angular multipoles B_l^m(k1, mu, t) of the redshift-space
+ * bispectrum of a gridded periodic field with the plane x annular-ring FFT
+ * estimator of Gill & Bharadwaj (arXiv:2405.14513, Sec. II):
+ *
+ *   Delta(k)      forward 3-D DFT of delta(x), Delta = (V/N_g^3) DFT       (Sec. II)
+ *   D(r, n, x)    sum over ring r of plane n of Delta(u, n) e^{-i u.x}     (Eq. 9)
+ *   S(c)          sum_x D(r1,n1,x) D(r2,n2,x) D(r3,n3,x), n1+n2+n3 = 0     (Eq. 8)
+ *   N_tri(c)      number of closed (u, v, w) in the three rings             (Eq. 10)
+ *   B_l^m(bin)    sqrt((2l+1)/4pi) sum Y* B_hat N_tri / sum |Y|^2 N_tri     (Eq. 13)
+ *
+ * Conventions (the paper leaves these open; the library fixes them):
+ *   - wave vectors are integer lattice vectors, k in units of k_f = 2 pi / L;
+ *     z (the fastest grid index) is the line of sight;
+ *   - ring edges R_0 = 0, R_r = R_{r-1} + 2^floor((r-1)/10), last edge clipped
+ *     to N_g/3, membership R_{r-1} <= |u| < R_r; mean radius = average |u|;
+ *   - a combination is a multiset of three (ring, plane) sides with
+ *     n1 + n2 + n3 = 0 and N_tri > 0, kept if k1 in [k1_min, k1_max) and
+ *     mu, t in [0.5, 1] on the mean-value sides (Eq. 2);
+ *   - Y* is replaced by its average over the two mirror images that every ring
+ *     combination contains, N_lm P_l^m(p_z) cos(m phi) (Eq. 3 orientation,
+ *     p_y >= 0), averaged over labellings of sides with equal k;
+ *   - outputs are the even-l multipoles 0 <= m <= min(l, m_max), l <= l_max,
+ *     ordered by l then m (16 values for l_max = m_max = 6); empty bins are NaN.
+ *
+ * Error behaviour: every call returns a bk_status; 0 is success.  Nothing is
+ * thrown across the ABI.  bk_last_error() returns a message for the last
+ * failing call on the calling thread (valid until that thread's next call).
+ *
+ * Ownership: the caller owns every host buffer it passes and every device
+ * buffer it passes as input.  A plan owns all device memory it allocates and
+ * releases it in bk_plan_destroy.  get_* calls copy into caller buffers and
+ * fail with BK_ERR_SIZE if the capacity (in elements) is too small.
+ */
+#ifndef BK_H
+#define BK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bk_plan_s* bk_plan;
+
+typedef enum { BK_F32 = 1, BK_F64 = 2 } bk_prec;
+
+typedef enum {
+  BK_OK = 0,
+  BK_ERR_ARG = -1,   /* invalid argument (sizes, ranges, null pointers)          */
+  BK_ERR_STATE = -2, /* call out of order (e.g. estimate before a grid is loaded) */
+  BK_ERR_SIZE = -3,  /* caller buffer too small                                  */
+  BK_ERR_OOM = -4,   /* device or host allocation failed                         */
+  BK_ERR_HIP = -5    /* a HIP runtime call failed; bk_last_error has the reason  */
+} bk_status;
+
+/* Second-level binning and outputs (Eq. 13).  k1 limits in units of k_f. */
+typedef struct {
+  int ng;            /* N_g per side: 2^a or 3*2^a, a multiple of 8, 8 <= N_g <= 512     */
+  double box_len;    /* L (V = L^3); <= 0 means L = N_g (unit cell)                       */
+  int n_k1;          /* linear k1 bins on [k1_min, k1_max)                                 */
+  double k1_min;     /* >= 0                                                               */
+  double k1_max;     /* <= N_g / 3 (periodic-box limit of the rings)                       */
+  int n_mu;          /* linear mu bins on [0.5, 1], top bin closed                         */
+  int n_t;           /* linear t bins on [0.5, 1], top bin closed                          */
+  int l_max;         /* <= 12                                                              */
+  int m_max;         /* <= l_max                                                           */
+  int even_l_only;   /* must be 1 (odd l vanish for a real field with this weighting)      */
+} bk_binning;
+
+/* Build the geometry tables (rings, N_tri, combinations, weights, bins) on the
+ * host and allocate the device working set on `device` for up to `max_batch`
+ * fields of this size.  prec selects float32 (BK_F32: FFTs, D and the products
+ * in float32, blocked float32 partial sums combined in float64) or float64
+ * (BK_F64: every step in float64).  The final per-bin sums are float64 in both. */
+bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int max_batch, bk_plan* out);
+bk_status bk_plan_destroy(bk_plan plan);
+
+/* Copy `batch` fields delta(x), C order [batch][x][y][z] (z = line of sight),
+ * of type dtype (BK_F32 or BK_F64), into the plan.  `delta` is a device pointer
+ * if is_device_ptr != 0, else a host pointer.  The copy is enqueued on
+ * hip_stream (a hipStream_t, NULL = default stream); a device input must stay
+ * valid until the stream reaches this point. */
+bk_status bk_load_grid(bk_plan plan, const void* delta, int dtype, int batch, int is_device_ptr,
+                       void* hip_stream);
+
+/* Enqueue the whole estimator for the loaded fields on hip_stream:
+ * forward FFT, ring-masked 2-D FFTs (Step I), triple-product sums (Step II)
+ * and the binned multipoles.  Asynchronous; results are read with get_*. */
+bk_status bk_estimate(bk_plan plan, void* hip_stream);
+
+/* Wait for all work the plan enqueued. */
+bk_status bk_synchronize(bk_plan plan);
+
+/* Output sizes: number of (l, m) pairs and bins per axis. */
+bk_status bk_query_sizes(bk_plan plan, int* n_lm, int* n_k1, int* n_mu, int* n_t);
+
+/* (l, m) of each output row, as pairs: lm_pairs[2 i] = l, lm_pairs[2 i + 1] = m. cap >= 2 n_lm. */
+bk_status bk_get_lm_list(bk_plan plan, int* lm_pairs, size_t cap);
+
+/* B_l^m as float64 [batch][n_lm][n_k1][n_mu][n_t] for the last estimate
+ * (synchronises the plan's stream).  cap >= batch * n_lm * n_bins. */
+bk_status bk_get_multipoles(bk_plan plan, double* out, size_t cap);
+
+/* Sum of N_tri over the combinations of each bin, int64 [n_k1][n_mu][n_t].
+ * Geometry only (independent of the field); exact. */
+bk_status bk_get_triangle_counts(bk_plan plan, int64_t* out, size_t cap);
+
+/* N_tri-weighted mean (k1, mu, t) of each bin, float64 [n_bins][3]; NaN if empty. */
+bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
+
+/* Plan statistics, float64 [8]: combinations, work items, sides, rings,
+ * dense products per field (contraction terms incl. padding), useful products,
+ * device bytes held, number of canonical plane triples. */
+bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
+
+/* Device time of each stage of the last estimate in milliseconds, float64 [4]:
+ * forward FFT, ring FFTs, triple products, binning (hipEvents on the stream). */
+bk_status bk_get_stage_times(bk_plan plan, double* ms, size_t cap);
+
+/* Host-only geometry (no device needed): the same per-bin sums of N_tri that
+ * bk_get_triangle_counts returns, int64 [n_k1][n_mu][n_t], and optionally the
+ * number of kept combinations (counting an n -> -n partner pair once).  Useful
+ * to inspect a binning before committing device memory. */
+bk_status bk_count_triangles(const bk_binning* binning, int64_t* out, size_t cap, int64_t* n_combinations);
+
+/* Test support: copy an intermediate device buffer of the last estimate into
+ * host memory.  which = 0: Delta planes, complex [batch][nkeep][N][N] (scaled
+ * by N^-3/2, planes n = 0..nkeep-1, indices u mod N); 1: D of the stored sides
+ * n >= 0, complex [batch][n_sides][N][N] (x_perp index x * N + y); 2: the
+ * side table, int32 [n_sides][2] = (ring, n).  Elements are float32 pairs for
+ * BK_F32 plans, float64 pairs for BK_F64.  *needed receives the size in bytes;
+ * BK_ERR_SIZE if cap_bytes is smaller. */
+bk_status bk_debug_get_buffer(bk_plan plan, int which, void* out, size_t cap_bytes, size_t* needed);
+
+/* Test support: runs one 16x16x4 MFMA of the given precision (BK_F32 or BK_F64)
+ * with A[i][k] = i + 16 k and B[k][j] = 1 if j == k else 0 (k < 4), and returns
+ * per lane the four accumulator values, float64 [64][4], so tests can check
+ * the lane layout the contraction kernel assumes. */
+bk_status bk_debug_mfma_probe(int prec, double* out, size_t cap);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* bk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BK_H */

@@ -1,0 +1,581 @@
+// C ABI of the estimator: plan, device memory, launches (include/bk.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bk.h"
+#include "bk_kernels.hpp"
+#include "bk_tables.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bk_status fail(bk_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define BK_HIP(call)                                                                                     \
+  do {                                                                                                   \
+    hipError_t e_ = (call);                                                                              \
+    if (e_ != hipSuccess)                                                                                \
+      return fail(e_ == hipErrorOutOfMemory ? BK_ERR_OOM : BK_ERR_HIP,                                   \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                                    \
+  } while (0)
+
+bool fft_shape(int n, bk::FftShape* sh) {
+  sh->n = n;
+  sh->nstages = 0;
+  int m = n;
+  if (m % 3 == 0) m /= 3;
+  if (m < 2 || (m & (m - 1)) != 0) return false;
+  while (m % 4 == 0) {
+    sh->radix[sh->nstages++] = 4;
+    m /= 4;
+  }
+  if (m == 2) sh->radix[sh->nstages++] = 2;
+  if (n % 3 == 0) sh->radix[sh->nstages++] = 3;
+  return true;
+}
+
+}  // namespace
+
+struct bk_plan_s {
+  bk::Tables tab;
+  int prec = BK_F64;
+  int device = 0;
+  int max_batch = 1;
+  int batch = 0;          // fields currently loaded
+  int in_dtype = 0;       // dtype of the loaded fields
+  int estimated = 0;      // a completed estimate is enqueued for `batch`
+  hipStream_t stream = nullptr;
+  size_t elem = 8;        // sizeof(complex T) / 2
+  bk::FftShape sh{};
+  int nkeep = 0;
+  long g_total = 0;       // complex elements of G per field
+  long n_sides = 0;
+  long X = 0;
+  long n_items = 0;
+  double norm = 0.0;
+  double delta_scale = 1.0;
+  size_t lds_k3 = 0;
+  size_t bytes = 0;
+
+  void* d_in = nullptr;       // [max_batch][N^3] of the input dtype
+  void* d_F = nullptr;        // [max_batch][nkeep][N][N] complex
+  void* d_G = nullptr;        // [max_batch][g_total] complex
+  void* d_D = nullptr;        // [max_batch][n_sides][N^2] complex
+  double* d_S = nullptr;      // [max_batch][n_items][512]
+  double* d_B = nullptr;      // [max_batch][n_lm][n_bins]
+  void* d_tw = nullptr;       // twiddles, N complex
+  bk::GroupDesc* d_groups = nullptr;
+  bk::ItemDesc* d_items = nullptr;
+  int32_t* d_group_sides = nullptr;
+  int32_t* d_mode_ring = nullptr;
+  int32_t* d_side_ring = nullptr;
+  int32_t* d_side_plane = nullptr;
+  int32_t* d_side_u = nullptr;
+  long* d_goff = nullptr;
+  bk::K2Line* d_k2lines = nullptr;
+  long n_k2lines = 0;
+  long* d_bin_ptr = nullptr;
+  long* d_combo_slot = nullptr;
+  double* d_coef = nullptr;
+  unsigned char* d_empty = nullptr;
+  hipEvent_t ev[5] = {};
+  bool have_events = false;
+};
+
+namespace {
+
+bk_status dalloc(bk_plan p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  const char* cap = std::getenv("BK_MAX_DEVICE_BYTES");
+  if (cap && p->bytes + bytes > size_t(std::strtoull(cap, nullptr, 10)))
+    return fail(BK_ERR_OOM, "device allocation exceeds BK_MAX_DEVICE_BYTES");
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(e == hipErrorOutOfMemory ? BK_ERR_OOM : BK_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  p->bytes += bytes;
+  return BK_OK;
+}
+
+template <typename V>
+bk_status put(bk_plan p, V** dptr, const V* host, size_t count) {
+  bk_status st = dalloc(p, reinterpret_cast<void**>(dptr), count * sizeof(V));
+  if (st != BK_OK) return st;
+  if (count) BK_HIP(hipMemcpy(*dptr, host, count * sizeof(V), hipMemcpyHostToDevice));
+  return BK_OK;
+}
+
+void release(bk_plan p) {
+  void* ptrs[] = {p->d_in,         p->d_F,          p->d_G,          p->d_D,          p->d_S,
+                  p->d_B,          p->d_tw,         p->d_groups,     p->d_items,      p->d_group_sides,
+                  p->d_mode_ring,  p->d_side_ring,  p->d_side_plane, p->d_side_u,     p->d_goff,
+                  p->d_k2lines,    p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (p->have_events)
+    for (auto& e : p->ev) (void)hipEventDestroy(e);
+}
+
+int pick_tb(int n, size_t elem_bytes) {
+  // two LDS buffers of tb lines, at most 64 KiB, tb divides n
+  int tb = 16;
+  while (tb > 1 && (size_t(2) * tb * n * elem_bytes > 65536 || n % tb != 0)) tb /= 2;
+  return tb;
+}
+
+template <typename T>
+bk_status launch_all(bk_plan p, hipStream_t st) {
+  using C = bk::cplx<T>;
+  const int n = p->sh.n;
+  const int B = p->batch;
+  const size_t cs = sizeof(C);
+  const int tb = pick_tb(n, cs);
+  const size_t lds_fft = size_t(2) * tb * n * cs;
+  const C* tw = reinterpret_cast<const C*>(p->d_tw);
+  C* F = reinterpret_cast<C*>(p->d_F);
+  C* G = reinterpret_cast<C*>(p->d_G);
+  C* D = reinterpret_cast<C*>(p->d_D);
+
+  BK_HIP(hipEventRecord(p->ev[0], st));
+  // K1: z pass (real input), y rows, x columns
+  {
+    dim3 grid(n * (n / tb), B);
+    if (p->in_dtype == BK_F32)
+      hipLaunchKernelGGL((bk::k1_z_kernel<T, float>), grid, dim3(256), lds_fft, st,
+                         reinterpret_cast<const float*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+    else
+      hipLaunchKernelGGL((bk::k1_z_kernel<T, double>), grid, dim3(256), lds_fft, st,
+                         reinterpret_cast<const double*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+    BK_HIP(hipGetLastError());
+    const long lines = long(B) * p->nkeep * n;
+    hipLaunchKernelGGL((bk::k_rows_kernel<T>), dim3((lines + tb - 1) / tb), dim3(256), lds_fft, st, F, tw, p->sh,
+                       tb, lines);
+    BK_HIP(hipGetLastError());
+    hipLaunchKernelGGL((bk::k_cols_kernel<T>), dim3(n / tb, B * p->nkeep), dim3(256), lds_fft, st, F, tw, p->sh, tb);
+    BK_HIP(hipGetLastError());
+  }
+  BK_HIP(hipEventRecord(p->ev[1], st));
+  // K2: ring rows, then columns
+  if (p->n_sides > 0) {
+    dim3 g1((p->n_k2lines + tb - 1) / tb, B);
+    hipLaunchKernelGGL((bk::k2_rows_kernel<T>), g1, dim3(256), lds_fft, st, F, G, p->d_k2lines, p->n_k2lines,
+                       p->d_side_ring, p->d_side_plane, p->d_side_u, p->d_goff, p->g_total, p->d_mode_ring,
+                       p->tab.lim, p->nkeep, tw, p->sh, tb);
+    BK_HIP(hipGetLastError());
+    dim3 g2(p->n_sides * (n / tb), B);
+    hipLaunchKernelGGL((bk::k2_cols_kernel<T>), g2, dim3(256), lds_fft, st, G, D, p->d_side_u, p->d_goff, p->g_total,
+                       int(p->n_sides), tw, p->sh, tb);
+    BK_HIP(hipGetLastError());
+  }
+  BK_HIP(hipEventRecord(p->ev[2], st));
+  // K3: triple products
+  if (!p->tab.groups.empty()) {
+    dim3 g3(p->tab.groups.size(), B);
+    hipLaunchKernelGGL((bk::k3_contract_kernel<T>), g3, dim3(64 * bk::kItemsPerGroup), p->lds_k3, st, D,
+                       p->n_sides, p->d_groups, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
+    BK_HIP(hipGetLastError());
+  }
+  BK_HIP(hipEventRecord(p->ev[3], st));
+  // K4: binning
+  {
+    const int n_bins = p->tab.bin.n_k1 * p->tab.bin.n_mu * p->tab.bin.n_t;
+    dim3 g4(n_bins, B);
+    hipLaunchKernelGGL(bk::k4_bin_kernel, g4, dim3(64), 0, st, p->d_S, p->n_items * long(bk::kItemOut), p->d_bin_ptr,
+                       p->d_combo_slot, p->d_coef, p->d_empty, int(p->tab.lm_l.size()), n_bins, p->norm, p->d_B);
+    BK_HIP(hipGetLastError());
+  }
+  BK_HIP(hipEventRecord(p->ev[4], st));
+  return BK_OK;
+}
+
+}  // namespace
+
+extern "C" const char* bk_last_error(void) { return g_last_error.c_str(); }
+
+namespace {
+
+bk_status check_binning(const bk_binning* bn, bk::FftShape* sh, bk::Binning* b) {
+  if (bn->ng < 8 || bn->ng > 512 || bn->ng % 8 != 0 || !fft_shape(bn->ng, sh))
+    return fail(BK_ERR_ARG, "ng must be 2^a or 3*2^a, a multiple of 8, with 8 <= ng <= 512");
+  if (bn->n_k1 < 1 || bn->n_mu < 1 || bn->n_t < 1) return fail(BK_ERR_ARG, "bin counts must be >= 1");
+  if (!(bn->k1_min >= 0.0) || !(bn->k1_max > bn->k1_min)) return fail(BK_ERR_ARG, "need 0 <= k1_min < k1_max");
+  if (bn->k1_max > double(bn->ng) / 3.0) return fail(BK_ERR_ARG, "k1_max must not exceed ng/3");
+  if (bn->l_max < 0 || bn->l_max > 12 || bn->m_max < 0 || bn->m_max > bn->l_max)
+    return fail(BK_ERR_ARG, "need 0 <= m_max <= l_max <= 12");
+  if (bn->even_l_only != 1) return fail(BK_ERR_ARG, "only even_l_only = 1 is supported");
+  if (!(bn->box_len >= 0.0) && !(bn->box_len < 0.0)) return fail(BK_ERR_ARG, "box_len is NaN");
+  b->ng = bn->ng;
+  b->box_len = bn->box_len > 0 ? bn->box_len : double(bn->ng);
+  b->n_k1 = bn->n_k1;
+  b->k1_min = bn->k1_min;
+  b->k1_max = bn->k1_max;
+  b->n_mu = bn->n_mu;
+  b->n_t = bn->n_t;
+  b->l_max = bn->l_max;
+  b->m_max = bn->m_max;
+  return BK_OK;
+}
+
+int host_threads() { return int(std::max(1u, std::min(16u, std::thread::hardware_concurrency()))); }
+
+}  // namespace
+
+extern "C" bk_status bk_count_triangles(const bk_binning* bn, int64_t* out, size_t cap, int64_t* n_comb) {
+  g_last_error.clear();
+  if (!bn || !out) return fail(BK_ERR_ARG, "null argument");
+  bk::FftShape sh{};
+  bk::Binning b;
+  bk_status st = check_binning(bn, &sh, &b);
+  if (st != BK_OK) return st;
+  const size_t n_bins = size_t(b.n_k1) * b.n_mu * b.n_t;
+  if (cap < n_bins) return fail(BK_ERR_SIZE, "output buffer too small");
+  bk::Tables T;
+  std::string err;
+  try {
+    err = bk::build_tables(b, host_threads(), &T);
+  } catch (const std::bad_alloc&) {
+    return fail(BK_ERR_OOM, "host allocation failed while building tables");
+  }
+  if (!err.empty()) return fail(BK_ERR_ARG, err);
+  std::copy(T.bin_count.begin(), T.bin_count.end(), out);
+  if (n_comb) *n_comb = T.n_combos;
+  return BK_OK;
+}
+
+extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, int max_batch, bk_plan* out) {
+  g_last_error.clear();
+  if (!bn || !out) return fail(BK_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (prec != BK_F32 && prec != BK_F64) return fail(BK_ERR_ARG, "prec must be BK_F32 or BK_F64");
+  if (max_batch < 1) return fail(BK_ERR_ARG, "max_batch must be >= 1");
+  bk::FftShape sh{};
+  bk::Binning b;
+  {
+    bk_status cst = check_binning(bn, &sh, &b);
+    if (cst != BK_OK) return cst;
+  }
+  int ndev = 0;
+  BK_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(BK_ERR_ARG, "no such device");
+  BK_HIP(hipSetDevice(device));
+
+  bk_plan p = new (std::nothrow) bk_plan_s();
+  if (!p) return fail(BK_ERR_OOM, "host allocation failed");
+  p->prec = prec;
+  p->device = device;
+  p->max_batch = max_batch;
+  p->sh = sh;
+  std::string err;
+  try {
+    err = bk::build_tables(b, host_threads(), &p->tab);
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return fail(BK_ERR_OOM, "host allocation failed while building tables");
+  }
+  if (!err.empty()) {
+    delete p;
+    return fail(BK_ERR_ARG, err);
+  }
+  bk::Tables& T = p->tab;
+  const int n = bn->ng;
+  p->X = long(n) * n;
+  p->nkeep = T.nmax + 1;
+  if (p->nkeep > n / 2 + 1) p->nkeep = n / 2 + 1;
+  p->n_sides = long(T.side_ring.size());
+  p->n_items = long(T.items.size());
+  p->elem = prec == BK_F32 ? 4 : 8;
+  const size_t cs = 2 * p->elem;
+  // scale so float32 sums stay far from overflow: Delta' = Delta_DFT / N^{3/2}
+  p->delta_scale = 1.0 / std::pow(double(n), 1.5);
+  const double vol = b.box_len * b.box_len * b.box_len;
+  const double n3 = double(n) * n * n;
+  // B = sqrt(.) Re sum w S_Delta / (V N^2) / den;  S_Delta = (V/N^3)^3 S_DFT;  S_DFT = S' / scale^3
+  p->norm = std::pow(vol / n3, 3) / (vol * double(n) * n) / std::pow(p->delta_scale, 3);
+
+  // K2 line list, row extents and G offsets
+  std::vector<int32_t> side_u(p->n_sides);
+  std::vector<long> goff(p->n_sides + 1, 0);
+  std::vector<bk::K2Line> lines;
+  for (long s = 0; s < p->n_sides; ++s) {
+    const int r = T.side_ring[s];
+    const int64_t e3 = T.edge3[r];
+    int U = 0;
+    while (9 * int64_t(U + 1) * (U + 1) < e3 * e3) ++U;  // largest |u_x| with |u_x| < R_r
+    side_u[s] = U;
+    goff[s + 1] = goff[s] + long(2 * U + 1) * n;
+    for (int ux = -U; ux <= U; ++ux) lines.push_back({int32_t(s), int32_t(ux)});
+  }
+  p->g_total = goff[p->n_sides];
+  p->n_k2lines = long(lines.size());
+
+  std::vector<double> twd(2 * size_t(n));
+  for (int t = 0; t < n; ++t) {
+    twd[2 * t] = std::cos(2.0 * M_PI * double(t) / double(n));
+    twd[2 * t + 1] = -std::sin(2.0 * M_PI * double(t) / double(n));
+  }
+  std::vector<float> twf(twd.begin(), twd.end());
+
+  bk_status st = BK_OK;
+  const int n_bins = b.n_k1 * b.n_mu * b.n_t;
+  const int nlm = int(T.lm_l.size());
+#define TRY(x)              \
+  do {                      \
+    st = (x);               \
+    if (st != BK_OK) {      \
+      release(p);           \
+      delete p;             \
+      return st;            \
+    }                       \
+  } while (0)
+  TRY(dalloc(p, &p->d_in, size_t(max_batch) * size_t(n3) * 8));
+  TRY(dalloc(p, &p->d_F, size_t(max_batch) * p->nkeep * size_t(n) * n * cs));
+  TRY(dalloc(p, &p->d_G, size_t(max_batch) * size_t(p->g_total) * cs));
+  TRY(dalloc(p, &p->d_D, size_t(max_batch) * size_t(p->n_sides) * size_t(p->X) * cs));
+  TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * bk::kItemOut * 8));
+  TRY(dalloc(p, reinterpret_cast<void**>(&p->d_B), size_t(max_batch) * nlm * n_bins * 8));
+  if (prec == BK_F32)
+    TRY(put(p, reinterpret_cast<float**>(&p->d_tw), twf.data(), twf.size()));
+  else
+    TRY(put(p, reinterpret_cast<double**>(&p->d_tw), twd.data(), twd.size()));
+  TRY(put(p, &p->d_groups, T.groups.data(), T.groups.size()));
+  TRY(put(p, &p->d_items, T.items.data(), T.items.size()));
+  TRY(put(p, &p->d_group_sides, T.group_sides.data(), T.group_sides.size()));
+  TRY(put(p, &p->d_mode_ring, T.mode_ring.data(), T.mode_ring.size()));
+  TRY(put(p, &p->d_side_ring, T.side_ring.data(), T.side_ring.size()));
+  TRY(put(p, &p->d_side_plane, T.side_plane.data(), T.side_plane.size()));
+  TRY(put(p, &p->d_side_u, side_u.data(), side_u.size()));
+  TRY(put(p, &p->d_goff, goff.data(), goff.size()));
+  TRY(put(p, &p->d_k2lines, lines.data(), lines.size()));
+  std::vector<long> bin_ptr(T.bin_ptr.begin(), T.bin_ptr.end());
+  std::vector<long> cslot(T.combo_slot.begin(), T.combo_slot.end());
+  TRY(put(p, &p->d_bin_ptr, bin_ptr.data(), bin_ptr.size()));
+  TRY(put(p, &p->d_combo_slot, cslot.data(), cslot.size()));
+  TRY(put(p, &p->d_coef, T.combo_coef.data(), T.combo_coef.size()));
+  TRY(put(p, &p->d_empty, T.bin_empty_lm.data(), T.bin_empty_lm.size()));
+#undef TRY
+  // the host copies of the per-combination arrays are no longer needed
+  std::vector<double>().swap(T.combo_coef);
+  std::vector<int64_t>().swap(T.combo_slot);
+
+  p->lds_k3 = size_t(T.max_group_sides) * bk::kLdsStride * cs;
+  if (p->lds_k3 > 65536) {
+    release(p);
+    delete p;
+    return fail(BK_ERR_ARG, "workgroup staging exceeds 64 KiB of LDS");
+  }
+  for (auto& e : p->ev) {
+    hipError_t he = hipEventCreate(&e);
+    if (he != hipSuccess) {
+      release(p);
+      delete p;
+      return fail(BK_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+  }
+  p->have_events = true;
+  *out = p;
+  return BK_OK;
+}
+
+extern "C" {
+
+bk_status bk_plan_destroy(bk_plan p) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  (void)hipSetDevice(p->device);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  (void)hipDeviceSynchronize();
+  release(p);
+  delete p;
+  return BK_OK;
+}
+
+bk_status bk_load_grid(bk_plan p, const void* delta, int dtype, int batch, int is_device_ptr, void* hip_stream) {
+  g_last_error.clear();
+  if (!p || !delta) return fail(BK_ERR_ARG, "null argument");
+  if (dtype != BK_F32 && dtype != BK_F64) return fail(BK_ERR_ARG, "dtype must be BK_F32 or BK_F64");
+  if (batch < 1 || batch > p->max_batch) return fail(BK_ERR_ARG, "batch must be in [1, max_batch]");
+  BK_HIP(hipSetDevice(p->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t n3 = size_t(p->sh.n) * p->sh.n * p->sh.n;
+  const size_t bytes = size_t(batch) * n3 * (dtype == BK_F32 ? 4 : 8);
+  BK_HIP(hipMemcpyAsync(p->d_in, delta, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (!is_device_ptr) BK_HIP(hipStreamSynchronize(st));
+  p->batch = batch;
+  p->in_dtype = dtype;
+  p->estimated = 0;
+  p->stream = st;
+  return BK_OK;
+}
+
+bk_status bk_estimate(bk_plan p, void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  if (p->batch < 1) return fail(BK_ERR_STATE, "no grid loaded");
+  BK_HIP(hipSetDevice(p->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  bk_status s = p->prec == BK_F32 ? launch_all<float>(p, st) : launch_all<double>(p, st);
+  if (s != BK_OK) return s;
+  p->stream = st;
+  p->estimated = 1;
+  return BK_OK;
+}
+
+bk_status bk_synchronize(bk_plan p) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  BK_HIP(hipSetDevice(p->device));
+  BK_HIP(hipStreamSynchronize(p->stream));
+  return BK_OK;
+}
+
+bk_status bk_query_sizes(bk_plan p, int* n_lm, int* n_k1, int* n_mu, int* n_t) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  if (n_lm) *n_lm = int(p->tab.lm_l.size());
+  if (n_k1) *n_k1 = p->tab.bin.n_k1;
+  if (n_mu) *n_mu = p->tab.bin.n_mu;
+  if (n_t) *n_t = p->tab.bin.n_t;
+  return BK_OK;
+}
+
+bk_status bk_get_lm_list(bk_plan p, int* lm, size_t cap) {
+  g_last_error.clear();
+  if (!p || !lm) return fail(BK_ERR_ARG, "null argument");
+  const size_t need = 2 * p->tab.lm_l.size();
+  if (cap < need) return fail(BK_ERR_SIZE, "lm buffer too small");
+  for (size_t j = 0; j < p->tab.lm_l.size(); ++j) {
+    lm[2 * j] = p->tab.lm_l[j];
+    lm[2 * j + 1] = p->tab.lm_m[j];
+  }
+  return BK_OK;
+}
+
+bk_status bk_get_multipoles(bk_plan p, double* out, size_t cap) {
+  g_last_error.clear();
+  if (!p || !out) return fail(BK_ERR_ARG, "null argument");
+  if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run for the loaded grid");
+  const size_t n_bins = size_t(p->tab.bin.n_k1) * p->tab.bin.n_mu * p->tab.bin.n_t;
+  const size_t need = size_t(p->batch) * p->tab.lm_l.size() * n_bins;
+  if (cap < need) return fail(BK_ERR_SIZE, "output buffer too small");
+  BK_HIP(hipSetDevice(p->device));
+  BK_HIP(hipStreamSynchronize(p->stream));
+  BK_HIP(hipMemcpy(out, p->d_B, need * sizeof(double), hipMemcpyDeviceToHost));
+  return BK_OK;
+}
+
+bk_status bk_get_triangle_counts(bk_plan p, int64_t* out, size_t cap) {
+  g_last_error.clear();
+  if (!p || !out) return fail(BK_ERR_ARG, "null argument");
+  if (cap < p->tab.bin_count.size()) return fail(BK_ERR_SIZE, "output buffer too small");
+  std::copy(p->tab.bin_count.begin(), p->tab.bin_count.end(), out);
+  return BK_OK;
+}
+
+bk_status bk_get_bin_means(bk_plan p, double* out, size_t cap) {
+  g_last_error.clear();
+  if (!p || !out) return fail(BK_ERR_ARG, "null argument");
+  if (cap < p->tab.bin_mean.size()) return fail(BK_ERR_SIZE, "output buffer too small");
+  std::copy(p->tab.bin_mean.begin(), p->tab.bin_mean.end(), out);
+  return BK_OK;
+}
+
+bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
+  g_last_error.clear();
+  if (!p || !info) return fail(BK_ERR_ARG, "null argument");
+  if (cap < 8) return fail(BK_ERR_SIZE, "info buffer needs 8 entries");
+  info[0] = double(p->tab.n_combos);
+  info[1] = double(p->n_items);
+  info[2] = double(p->n_sides);
+  info[3] = double(p->tab.nr);
+  info[4] = p->tab.dense_terms;
+  info[5] = p->tab.useful_terms;
+  info[6] = double(p->bytes);
+  info[7] = double(p->tab.n_canonical_planes);
+  return BK_OK;
+}
+
+bk_status bk_get_stage_times(bk_plan p, double* ms, size_t cap) {
+  g_last_error.clear();
+  if (!p || !ms) return fail(BK_ERR_ARG, "null argument");
+  if (cap < 4) return fail(BK_ERR_SIZE, "need 4 entries");
+  if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run");
+  BK_HIP(hipSetDevice(p->device));
+  BK_HIP(hipEventSynchronize(p->ev[4]));
+  for (int i = 0; i < 4; ++i) {
+    float t = 0.f;
+    BK_HIP(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
+    ms[i] = double(t);
+  }
+  return BK_OK;
+}
+
+bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes, size_t* needed) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  const size_t cs = 2 * p->elem;
+  const size_t n2 = size_t(p->sh.n) * p->sh.n;
+  size_t bytes = 0;
+  const void* src = nullptr;
+  std::vector<int32_t> table;
+  if (which == 0) {
+    bytes = size_t(p->batch) * p->nkeep * n2 * cs;
+    src = p->d_F;
+  } else if (which == 1) {
+    bytes = size_t(p->batch) * size_t(p->n_sides) * n2 * cs;
+    src = p->d_D;
+  } else if (which == 2) {
+    for (long s = 0; s < p->n_sides; ++s) {
+      table.push_back(p->tab.side_ring[s]);
+      table.push_back(p->tab.side_plane[s]);
+    }
+    bytes = table.size() * sizeof(int32_t);
+  } else {
+    return fail(BK_ERR_ARG, "which must be 0, 1 or 2");
+  }
+  if (needed) *needed = bytes;
+  if (!out) return BK_OK;
+  if (cap_bytes < bytes) return fail(BK_ERR_SIZE, "output buffer too small");
+  if (which == 2) {
+    std::memcpy(out, table.data(), bytes);
+    return BK_OK;
+  }
+  if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run");
+  BK_HIP(hipSetDevice(p->device));
+  BK_HIP(hipStreamSynchronize(p->stream));
+  BK_HIP(hipMemcpy(out, src, bytes, hipMemcpyDeviceToHost));
+  return BK_OK;
+}
+
+bk_status bk_debug_mfma_probe(int prec, double* out, size_t cap) {
+  g_last_error.clear();
+  if (!out) return fail(BK_ERR_ARG, "null argument");
+  if (cap < 256) return fail(BK_ERR_SIZE, "need 256 entries");
+  if (prec != BK_F32 && prec != BK_F64) return fail(BK_ERR_ARG, "prec must be BK_F32 or BK_F64");
+  double* d = nullptr;
+  BK_HIP(hipMalloc(&d, 256 * sizeof(double)));
+  if (prec == BK_F32)
+    hipLaunchKernelGGL(bk::mfma_probe_kernel<float>, dim3(1), dim3(64), 0, 0, d);
+  else
+    hipLaunchKernelGGL(bk::mfma_probe_kernel<double>, dim3(1), dim3(64), 0, 0, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(BK_ERR_HIP, std::string("mfma probe: ") + hipGetErrorString(e));
+  return BK_OK;
+}
+
+}  // extern "C"

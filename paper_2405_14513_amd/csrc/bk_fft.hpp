@@ -1,0 +1,110 @@
+// LDS-resident Stockham FFT building blocks for gfx950 (HIP).
+//
+// All transforms here are forward DFTs, y[k] = sum_j x[j] e^{-2 pi i j k / N}:
+// the 3-D transform of the field (Sec. II) and the ring sums of Eq. 9, whose
+// exponent carries the same minus sign.  N = 2^a 3^b with b <= 1; stages use
+// radix 4, then one radix 2 if a is odd, then one radix 3.  Twiddles are a
+// table exp(-2 pi i t / N), t < N, computed on the host in float64 and cast.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bk {
+
+template <typename T>
+struct cplx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+
+struct FftShape {
+  int n;            // transform length
+  int nstages;
+  int radix[12];
+};
+
+// One Stockham pass over `lines` transforms held in LDS, src -> dst.
+// Element i of line l lives at buf[l * ls + i].
+template <typename T, int R>
+__device__ __forceinline__ void stockham_pass(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
+                                              const cplx<T>* __restrict__ tw, int n, int ns, int lines, int ls) {
+  const int nb = n / R;  // butterflies per line
+  const int total = lines * nb;
+  const int tw_step = n / (ns * R);
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int l = q / nb;
+    const int j = q - l * nb;
+    const int k = j % ns;
+    const cplx<T>* s = src + l * ls;
+    cplx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
+    if (ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(k * r * tw_step) % n]);
+    }
+    if constexpr (R == 2) {
+      const cplx<T> a = v[0], b = v[1];
+      v[0] = cadd(a, b);
+      v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+      // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
+      const T h = T(0.5);
+      const T s3 = T(0.86602540378443864676);
+      const cplx<T> t1 = cadd(v[1], v[2]);
+      const cplx<T> t2 = {v[0].x - h * t1.x, v[0].y - h * t1.y};
+      const cplx<T> t3 = {s3 * (v[1].y - v[2].y), -s3 * (v[1].x - v[2].x)};  // -i sqrt3/2 (v1 - v2)
+      v[0] = cadd(v[0], t1);
+      v[1] = cadd(t2, t3);
+      v[2] = csub(t2, t3);
+    } else if constexpr (R == 4) {
+      const cplx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+      const cplx<T> b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+      const cplx<T> mib1 = {b1.y, -b1.x};  // -i * b1
+      v[0] = cadd(a0, b0);
+      v[1] = cadd(a1, mib1);
+      v[2] = csub(a0, b0);
+      v[3] = csub(a1, mib1);
+    }
+    cplx<T>* d = dst + l * ls + (j / ns) * ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[r * ns] = v[r];
+  }
+}
+
+// Full transform of `lines` lines in LDS.  Returns the buffer holding the result.
+template <typename T>
+__device__ cplx<T>* lds_fft(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, const FftShape& sh, int lines, int ls) {
+  int ns = 1;
+  cplx<T>* src = b0;
+  cplx<T>* dst = b1;
+  for (int s = 0; s < sh.nstages; ++s) {
+    const int R = sh.radix[s];
+    if (R == 4)
+      stockham_pass<T, 4>(src, dst, tw, sh.n, ns, lines, ls);
+    else if (R == 2)
+      stockham_pass<T, 2>(src, dst, tw, sh.n, ns, lines, ls);
+    else
+      stockham_pass<T, 3>(src, dst, tw, sh.n, ns, lines, ls);
+    __syncthreads();
+    ns *= R;
+    cplx<T>* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+}  // namespace bk

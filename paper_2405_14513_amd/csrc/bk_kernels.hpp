@@ -1,0 +1,336 @@
+// Device kernels of the estimator (gfx950).
+//
+//  K1  forward 3-D DFT of the field, three batched 1-D passes (z, then y, then x),
+//      keeping only the k_parallel planes n = 0..nkeep-1 (Sec. II; negative
+//      planes follow from Delta(u, -n) = conj Delta(-u, n)).
+//  K2  ring sums D(r, n, x) of Eq. 9 as two pruned 1-D passes per side:
+//      rows |u_x| <= U_r along u_y, then columns along u_x.
+//  K3  triple-product sums S(c) = sum_x D D D of Eq. 8 for every kept
+//      combination, as MFMA 16x16x4 tiles: rows = (slot A, slot C) ring pairs,
+//      columns = slot-B rings, K = x_perp points staged through LDS.
+//  K4  second-level binning of Eq. 13: per bin, a fixed-order float64 sum of
+//      coefficient x Re S over the bin's combinations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bk_fft.hpp"
+#include "bk_tables.hpp"
+
+namespace bk {
+
+// ---------------------------------------------------------------- K1
+// z pass: real input lines delta[b][x][y][:] (contiguous), `tb` consecutive y
+// per block; writes F[b][n][x][y] for n < nkeep, scaled by `scale`.
+template <typename T, typename Tin>
+__global__ __launch_bounds__(256) void k1_z_kernel(const Tin* __restrict__ delta, cplx<T>* __restrict__ F,
+                                                   const cplx<T>* __restrict__ tw, FftShape sh, int tb, int nkeep,
+                                                   T scale) {
+  extern __shared__ char smem_raw[];
+  const int n = sh.n;
+  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b1 = b0 + tb * n;
+  const int ytiles = n / tb;
+  const int x = blockIdx.x / ytiles;
+  const int y0 = (blockIdx.x % ytiles) * tb;
+  const int b = blockIdx.y;
+  const size_t n3 = size_t(n) * n * n;
+  const Tin* src = delta + size_t(b) * n3 + (size_t(x) * n + y0) * n;
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) b0[q] = {T(src[q]) * scale, T(0)};
+  __syncthreads();
+  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  cplx<T>* dst = F + size_t(b) * nkeep * n * n + size_t(x) * n + y0;
+  for (int q = threadIdx.x; q < tb * nkeep; q += blockDim.x) {
+    const int kz = q / tb, l = q - kz * tb;
+    dst[size_t(kz) * n * n + l] = res[l * n + kz];
+  }
+}
+
+// In-place transform of contiguous lines: line i of `lines` at base + i * n.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_kernel(cplx<T>* __restrict__ data, const cplx<T>* __restrict__ tw,
+                                                     FftShape sh, int tb, long lines_total) {
+  extern __shared__ char smem_raw[];
+  const int n = sh.n;
+  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b1 = b0 + tb * n;
+  const long line0 = long(blockIdx.x) * tb;
+  const int lines = int(min(long(tb), lines_total - line0));
+  cplx<T>* base = data + line0 * n;
+  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) b0[q] = base[q];
+  __syncthreads();
+  cplx<T>* res = lds_fft(b0, b1, tw, sh, lines, n);
+  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) base[q] = res[q];
+}
+
+// In-place transform of strided lines: for each plane p (grid.y), the lines are
+// the columns c of an n x n array (element i at i * n + c); `tb` columns per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data, const cplx<T>* __restrict__ tw,
+                                                     FftShape sh, int tb) {
+  extern __shared__ char smem_raw[];
+  const int n = sh.n;
+  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b1 = b0 + tb * n;
+  const int c0 = blockIdx.x * tb;
+  cplx<T>* base = data + size_t(blockIdx.y) * n * n + c0;
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+    const int i = q / tb, l = q - i * tb;
+    b0[l * n + i] = base[size_t(i) * n + l];
+  }
+  __syncthreads();
+  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+    const int i = q / tb, l = q - i * tb;
+    base[size_t(i) * n + l] = res[l * n + i];
+  }
+}
+
+// ---------------------------------------------------------------- K2
+struct K2Line {
+  int32_t side;
+  int32_t ux;  // signed row
+};
+
+// Rows: for each listed (side, u_x), transform the ring-masked row of plane
+// n(side) along u_y into G[goff[side] + (u_x + U) * n + y].
+template <typename T>
+__global__ __launch_bounds__(256) void k2_rows_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ G,
+                                                      const K2Line* __restrict__ lines, long n_lines,
+                                                      const int32_t* __restrict__ side_ring,
+                                                      const int32_t* __restrict__ side_plane,
+                                                      const int32_t* __restrict__ side_u,
+                                                      const long* __restrict__ goff, long g_total,
+                                                      const int32_t* __restrict__ mode_ring, int lim, int nkeep,
+                                                      const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
+  extern __shared__ char smem_raw[];
+  const int n = sh.n;
+  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b1 = b0 + tb * n;
+  const long l0 = long(blockIdx.x) * tb;
+  const int cnt = int(min(long(tb), n_lines - l0));
+  const int b = blockIdx.y;
+  const cplx<T>* Fb = F + size_t(b) * nkeep * n * n;
+  const int side_len = 2 * lim + 1;
+  for (int q = threadIdx.x; q < cnt * n; q += blockDim.x) {
+    const int l = q / n, uyi = q - l * n;
+    const K2Line ln = lines[l0 + l];
+    const int uy = uyi <= n / 2 ? uyi : uyi - n;
+    cplx<T> v = {T(0), T(0)};
+    if (uy >= -lim && uy <= lim && mode_ring[(ln.ux + lim) * side_len + (uy + lim)] == side_ring[ln.side]) {
+      const int uxi = ln.ux < 0 ? ln.ux + n : ln.ux;
+      v = Fb[(size_t(side_plane[ln.side]) * n + uxi) * n + uyi];
+    }
+    b0[l * n + uyi] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = lds_fft(b0, b1, tw, sh, cnt, n);
+  cplx<T>* Gb = G + size_t(b) * g_total;
+  for (int q = threadIdx.x; q < cnt * n; q += blockDim.x) {
+    const int l = q / n, y = q - l * n;
+    const K2Line ln = lines[l0 + l];
+    Gb[goff[ln.side] + size_t(ln.ux + side_u[ln.side]) * n + y] = res[l * n + y];
+  }
+}
+
+// Columns: for side s = blockIdx.x / (n / tb) and tb consecutive y, transform
+// along u_x (rows |u_x| <= U stored in G, the rest zero) into D[b][s][x][y].
+template <typename T>
+__global__ __launch_bounds__(256) void k2_cols_kernel(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ D,
+                                                      const int32_t* __restrict__ side_u,
+                                                      const long* __restrict__ goff, long g_total, int n_sides,
+                                                      const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
+  extern __shared__ char smem_raw[];
+  const int n = sh.n;
+  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b1 = b0 + tb * n;
+  const int ytiles = n / tb;
+  const int s = blockIdx.x / ytiles;
+  const int y0 = (blockIdx.x % ytiles) * tb;
+  const int b = blockIdx.y;
+  const int U = side_u[s];
+  const cplx<T>* Gs = G + size_t(b) * g_total + goff[s];
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+    const int i = q / tb, l = q - i * tb;  // i = u_x index (mod n)
+    const int ux = i <= n / 2 ? i : i - n;
+    cplx<T> v = {T(0), T(0)};
+    if (ux >= -U && ux <= U) v = Gs[size_t(ux + U) * n + y0 + l];
+    b0[l * n + i] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  cplx<T>* Ds = D + (size_t(b) * n_sides + s) * size_t(n) * n;
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+    const int x = q / tb, l = q - x * tb;
+    Ds[size_t(x) * n + y0 + l] = res[l * n + x];
+  }
+}
+
+// ---------------------------------------------------------------- K3
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+// Operands: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  Result
+// register k of lane l holds column l % 16 and row out_row(l / 16, k); the two
+// instructions place rows differently (measured with mfma_probe_kernel).
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int kq, int k) { return 4 * kq + k; }
+};
+
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int out_row(int kq, int k) { return 4 * k + kq; }
+};
+
+constexpr int kLdsStride = kChunk + 1;  // complex elements per LDS slot (padded)
+constexpr int kItemOut = kPairsPerItem * kTileN;
+
+// One block = one GroupDesc (all on one canonical plane triple), one wave per
+// work item.  Every kChunk points of x_perp the block stages the group's sides
+// into LDS; each wave then forms the pair products P = D_A D_C (4 points per
+// lane group) and feeds Re P, Im P against Re D_B, -Im D_B into 16x16x4 MFMAs
+// (K = 4 points).  Partial sums of one chunk are added to float64 registers.
+template <typename T>
+__global__ __launch_bounds__(512) void k3_contract_kernel(const cplx<T>* __restrict__ D, long n_sides_total,
+                                                          const GroupDesc* __restrict__ groups,
+                                                          const ItemDesc* __restrict__ items,
+                                                          const int32_t* __restrict__ group_sides, long X,
+                                                          double* __restrict__ S_out, long n_items_total) {
+  extern __shared__ char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const GroupDesc gd = groups[blockIdx.x];
+  const int b = blockIdx.y;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 15;
+  const int kq = lane >> 4;
+  const cplx<T>* Db = D + size_t(b) * n_sides_total * X;
+
+  // zero slot
+  for (int i = threadIdx.x; i < kLdsStride; i += blockDim.x) lds[gd.n_sides * kLdsStride + i] = {T(0), T(0)};
+
+  const bool active = wave < gd.n_items;
+  int sa0 = 0, sc0 = 0, sa1 = 0, sc1 = 0, sb = 0;
+  if (active) {
+    const ItemDesc& it = items[gd.item_begin + wave];
+    sa0 = it.a_slot[row];
+    sc0 = it.c_slot[row];
+    sa1 = it.a_slot[16 + row];
+    sc1 = it.c_slot[16 + row];
+    sb = it.b_slot[row];
+  }
+  const T sgnA = (gd.conj_mask & 1) ? T(-1) : T(1);
+  const T sgnB = (gd.conj_mask & 2) ? T(-1) : T(1);
+  const T sgnC = (gd.conj_mask & 4) ? T(-1) : T(1);
+
+  typedef typename Mfma<T>::acc_t acc_t;
+  double out0[4] = {0, 0, 0, 0}, out1[4] = {0, 0, 0, 0};
+  const int nstage = gd.n_sides * kChunk;
+  for (long x0 = 0; x0 < X; x0 += kChunk) {
+    __syncthreads();
+    for (int q = threadIdx.x; q < nstage; q += blockDim.x) {
+      const int s = q / kChunk, i = q - s * kChunk;
+      lds[s * kLdsStride + i] = Db[size_t(group_sides[gd.side_begin + s]) * X + x0 + i];
+    }
+    __syncthreads();
+    if (active) {
+      acc_t r0 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < kChunk / 4; ++ks) {
+        const int xi = ks * 4 + kq;
+        const cplx<T> a0 = lds[sa0 * kLdsStride + xi];
+        const cplx<T> c0 = lds[sc0 * kLdsStride + xi];
+        const cplx<T> a1 = lds[sa1 * kLdsStride + xi];
+        const cplx<T> c1 = lds[sc1 * kLdsStride + xi];
+        const cplx<T> bv = lds[sb * kLdsStride + xi];
+        const cplx<T> p0 = cmul(cplx<T>{a0.x, sgnA * a0.y}, cplx<T>{c0.x, sgnC * c0.y});
+        const cplx<T> p1 = cmul(cplx<T>{a1.x, sgnA * a1.y}, cplx<T>{c1.x, sgnC * c1.y});
+        const T br = bv.x, bi = -sgnB * bv.y;  // Re(P B) = Re P Re B - Im P Im B
+        r0 = Mfma<T>::step(p0.x, br, r0);
+        r1 = Mfma<T>::step(p1.x, br, r1);
+        i0 = Mfma<T>::step(p0.y, bi, i0);
+        i1 = Mfma<T>::step(p1.y, bi, i1);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        out0[k] += double(r0[k]) + double(i0[k]);
+        out1[k] += double(r1[k]) + double(i1[k]);
+      }
+    }
+  }
+  if (active) {
+    double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kItemOut;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = Mfma<T>::out_row(kq, k);
+      o[r * kTileN + row] = out0[k];
+      o[(16 + r) * kTileN + row] = out1[k];
+    }
+  }
+}
+
+// Layout probe: one wave, A[i][k] = i + 16 k, B[k][j] = (j == k).
+template <typename T>
+__global__ __launch_bounds__(64) void mfma_probe_kernel(double* out) {
+  const int lane = threadIdx.x;
+  const int row = lane & 15, kq = lane >> 4;
+  const T a = T(row + 16 * kq);
+  const T bv = T(row == kq ? 1 : 0);
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+  acc = Mfma<T>::step(a, bv, acc);
+  for (int k = 0; k < 4; ++k) out[lane * 4 + k] = double(acc[k]);
+}
+
+// ---------------------------------------------------------------- K4
+// One wave per (bin, batch): B[b][j][bin] = norm * sum_c coef[c][j] * S[slot[c]].
+__global__ __launch_bounds__(64) void k4_bin_kernel(const double* __restrict__ S, long s_per_batch,
+                                                    const long* __restrict__ bin_ptr,
+                                                    const long* __restrict__ combo_slot,
+                                                    const double* __restrict__ coef,
+                                                    const unsigned char* __restrict__ empty, int n_lm, int n_bins,
+                                                    double norm, double* __restrict__ B) {
+  const int bin = blockIdx.x;
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x;
+  const long c0 = bin_ptr[bin], c1 = bin_ptr[bin + 1];
+  const double* Sb = S + size_t(b) * s_per_batch;
+  for (int j0 = 0; j0 < n_lm; j0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+    for (long c = c0 + lane; c < c1; c += 64) {
+      const double s = Sb[combo_slot[c]];
+      const double* cf = coef + size_t(c) * n_lm + j0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (j0 + j < n_lm) acc[j] += cf[j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      double v = acc[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      acc[j] = v;
+    }
+    if (lane == 0) {
+      for (int j = 0; j < 16 && j0 + j < n_lm; ++j) {
+        const int jj = j0 + j;
+        B[(size_t(b) * n_lm + jj) * n_bins + bin] =
+            empty[size_t(jj) * n_bins + bin] ? __builtin_nan("") : norm * acc[j];
+      }
+    }
+  }
+}
+
+}  // namespace bk

@@ -1,0 +1,491 @@
+// Host-side geometry and work decomposition (see bk_tables.hpp).
+//
+// Paper references: rings and the N_g/3 cap (Sec. II, implementation
+// paragraph), N_tri (Eq. 10), the shape parameters (Eq. 2), the orientation
+// (Eq. 3), and the second-level binning (Eq. 13).  The readings fixed here
+// are listed in include/bk.h.
+#include "bk_tables.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <thread>
+
+namespace bk {
+
+namespace {
+
+constexpr double kDegenerateS = 1e-12;
+
+// |u|^2 = q lies below edge e (given as 3 * edge): 9 q < e3^2.
+inline bool below(int64_t q, int64_t e3) { return 9 * q < e3 * e3; }
+
+// Associated Legendre P_l^m(x) with the Condon-Shortley phase, by the
+// standard upward recurrence in l at fixed m.
+void legendre_table(int l_max, double x, std::vector<double>* p /* [(l_max+1)^2], p[l*(l_max+1)+m] */) {
+  const int L = l_max + 1;
+  p->assign(L * L, 0.0);
+  const double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+  double pmm = 1.0;
+  for (int m = 0; m <= l_max; ++m) {
+    if (m > 0) pmm *= -(2.0 * m - 1.0) * s;
+    (*p)[m * L + m] = pmm;
+    if (m + 1 <= l_max) (*p)[(m + 1) * L + m] = x * (2.0 * m + 1.0) * pmm;
+    for (int l = m + 2; l <= l_max; ++l) {
+      (*p)[l * L + m] = ((2.0 * l - 1.0) * x * (*p)[(l - 1) * L + m] - (l + m - 1.0) * (*p)[(l - 2) * L + m]) /
+                        double(l - m);
+    }
+  }
+}
+
+double norm_lm(int l, int m) {
+  double r = 1.0;  // (l-m)!/(l+m)!
+  for (int i = l - m + 1; i <= l + m; ++i) r /= double(i);
+  return std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * r);
+}
+
+struct Candidate {
+  int32_t ra, rb, rc;  // rings of slots A (plane a), B (plane b), C (plane -(a+b))
+};
+
+}  // namespace
+
+int count_lm(int l_max, int m_max) {
+  int n = 0;
+  for (int l = 0; l <= l_max; l += 2) n += std::min(l, m_max) + 1;
+  return n;
+}
+
+std::string build_tables(const Binning& b, int n_threads, Tables* out) {
+  Tables& T = *out;
+  T = Tables();
+  T.bin = b;
+  const int ng = b.ng;
+  T.ng = ng;
+  if (n_threads < 1) n_threads = 1;
+
+  // ---- rings: edges 3*R_r, widths 2^floor((r-1)/10), last edge clipped to N_g/3
+  T.edge3.push_back(0);
+  for (int r = 1;; ++r) {
+    int64_t nxt = T.edge3.back() + 3 * (int64_t(1) << ((r - 1) / 10));
+    if (nxt >= ng) {
+      T.edge3.push_back(ng);
+      break;
+    }
+    T.edge3.push_back(nxt);
+  }
+  const int nr = int(T.edge3.size()) - 1;
+  T.nr = nr;
+  const int lim = ng / 3 + 1;
+  T.lim = lim;
+  const int side_len = 2 * lim + 1;
+  T.mode_ring.assign(size_t(side_len) * side_len, 0);
+  std::vector<std::map<int64_t, int64_t>> shells(nr);
+  T.ring_count.assign(nr, 0);
+  for (int ux = -lim; ux <= lim; ++ux) {
+    for (int uy = -lim; uy <= lim; ++uy) {
+      const int64_t q = int64_t(ux) * ux + int64_t(uy) * uy;
+      for (int r = 1; r <= nr; ++r) {
+        if (!below(q, T.edge3[r - 1]) && below(q, T.edge3[r])) {
+          T.mode_ring[size_t(ux + lim) * side_len + (uy + lim)] = r;
+          shells[r - 1][q] += 1;
+          T.ring_count[r - 1] += 1;
+          break;
+        }
+      }
+    }
+  }
+  T.mean_radius.assign(nr, 0.0);
+  for (int r = 0; r < nr; ++r) {
+    if (T.ring_count[r] == 0) return "ring " + std::to_string(r + 1) + " holds no lattice mode";
+    double acc = 0.0;
+    for (const auto& kv : shells[r]) acc += double(kv.second) * std::sqrt(double(kv.first));
+    T.mean_radius[r] = acc / double(T.ring_count[r]);
+  }
+
+  // ---- N_tri(r1, r2, r3) (Eq. 10) by counting every (u, v) with w = -u - v in a ring
+  {
+    std::vector<int32_t> mx, my, mr;
+    for (int ux = -lim; ux <= lim; ++ux)
+      for (int uy = -lim; uy <= lim; ++uy) {
+        int r = T.mode_ring[size_t(ux + lim) * side_len + (uy + lim)];
+        if (r) {
+          mx.push_back(ux);
+          my.push_back(uy);
+          mr.push_back(r);
+        }
+      }
+    const size_t nm = mx.size();
+    const int W = 2 * lim;  // |w_x| <= 2 lim
+    const int wlen = 2 * W + 1;
+    std::vector<int32_t> wring(size_t(wlen) * wlen, 0);
+    for (int wx = -W; wx <= W; ++wx)
+      for (int wy = -W; wy <= W; ++wy)
+        if (std::abs(wx) <= lim && std::abs(wy) <= lim)
+          wring[size_t(wx + W) * wlen + (wy + W)] = T.mode_ring[size_t(wx + lim) * side_len + (wy + lim)];
+    const size_t nr1 = nr + 1;
+    std::vector<std::vector<int64_t>> partial(n_threads, std::vector<int64_t>(nr1 * nr1 * nr1, 0));
+    std::vector<std::thread> th;
+    for (int t = 0; t < n_threads; ++t) {
+      th.emplace_back([&, t]() {
+        auto& cnt = partial[t];
+        for (size_t i = t; i < nm; i += n_threads) {
+          const int ux = mx[i], uy = my[i];
+          const size_t base1 = size_t(mr[i]) * nr1 * nr1;
+          for (size_t j = 0; j < nm; ++j) {
+            const int wx = -ux - mx[j], wy = -uy - my[j];
+            const int r3 = wring[size_t(wx + W) * wlen + (wy + W)];
+            if (r3) cnt[base1 + size_t(mr[j]) * nr1 + r3] += 1;
+          }
+        }
+      });
+    }
+    for (auto& x : th) x.join();
+    T.ntri.assign(size_t(nr) * nr * nr, 0);
+    for (int r1 = 1; r1 <= nr; ++r1)
+      for (int r2 = 1; r2 <= nr; ++r2)
+        for (int r3 = 1; r3 <= nr; ++r3) {
+          int64_t s = 0;
+          for (int t = 0; t < n_threads; ++t) s += partial[t][(size_t(r1) * nr1 + r2) * nr1 + r3];
+          T.ntri[(size_t(r1 - 1) * nr + (r2 - 1)) * nr + (r3 - 1)] = s;
+        }
+  }
+
+  // ---- sides n >= 0 with mean-value k < k1_max; the k = 0 side is excluded
+  const int nmax = int(std::ceil(b.k1_max));
+  T.nmax = nmax;
+  T.side_of.assign(size_t(nmax + 1) * (nr + 1), -1);
+  for (int n = 0; n <= nmax; ++n)
+    for (int r = 1; r <= nr; ++r) {
+      if (r == 1 && n == 0) continue;
+      const double kk = T.mean_radius[r - 1];
+      const double q = kk * kk + double(n) * double(n);
+      if (std::sqrt(q) < b.k1_max) {
+        T.side_of[size_t(n) * (nr + 1) + r] = int32_t(T.side_ring.size());
+        T.side_ring.push_back(r);
+        T.side_plane.push_back(n);
+      }
+    }
+  auto side = [&](int r, int n_abs) -> int32_t {
+    if (n_abs > nmax || r < 1 || r > nr) return -1;
+    return T.side_of[size_t(n_abs) * (nr + 1) + r];
+  };
+
+  // ---- outputs
+  for (int l = 0; l <= b.l_max; l += 2)
+    for (int m = 0; m <= std::min(l, b.m_max); ++m) {
+      T.lm_l.push_back(l);
+      T.lm_m.push_back(m);
+    }
+  const int nlm = int(T.lm_l.size());
+  std::vector<double> nlm_norm(nlm), pref(nlm);
+  for (int j = 0; j < nlm; ++j) {
+    nlm_norm[j] = norm_lm(T.lm_l[j], T.lm_m[j]);
+    pref[j] = std::sqrt((2.0 * T.lm_l[j] + 1.0) / (4.0 * M_PI));
+  }
+  const int n_bins = b.n_k1 * b.n_mu * b.n_t;
+  const double dk = (b.k1_max - b.k1_min) / double(b.n_k1);
+  const double dmu = 0.5 / double(b.n_mu);
+  const double dt = 0.5 / double(b.n_t);
+
+  // ---- canonical plane triples (a, b, -(a+b)), a >= b >= 0, and their kept combinations.
+  // The partner with every n negated has conjugate S and, for even l, the same
+  // weight and bin; it is folded in through mult = 2 (1 when self-partnered).
+  struct PT {
+    int a, b;
+  };
+  std::vector<PT> pts;
+  for (int a = 0; a <= nmax; ++a)
+    for (int bb = 0; bb <= a; ++bb)
+      if (a + bb <= nmax) pts.push_back({a, bb});
+
+  struct ComboRec {
+    int32_t pt;  // index into pts
+    int32_t ra, rb, rc;
+    int32_t bin;
+    int32_t mult;
+    int64_t ntri;
+  };
+  std::vector<std::vector<ComboRec>> per_pt(pts.size());
+  std::vector<std::vector<double>> per_pt_w(pts.size()), per_pt_d(pts.size()), per_pt_kmt(pts.size());
+
+  std::atomic<size_t> next_pt{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < n_threads; ++t) {
+    th.emplace_back([&]() {
+      std::vector<double> P;
+      for (;;) {
+        const size_t ip = next_pt.fetch_add(1);
+        if (ip >= pts.size()) break;
+        const int a = pts[ip].a, bb = pts[ip].b, c = a + bb;
+        const int n_s[3] = {a, bb, -c};
+        for (int ra = 1; ra <= nr; ++ra) {
+          if (side(ra, a) < 0) continue;
+          for (int rb = 1; rb <= nr; ++rb) {
+            if (side(rb, bb) < 0) continue;
+            if (a == bb && rb < ra) continue;  // slots A and B share plane a: unordered
+            for (int rc = 1; rc <= nr; ++rc) {
+              if (side(rc, c) < 0) continue;
+              if (a == 0 && rc < rb) continue;        // (0,0,0): ra <= rb <= rc
+              if (bb == 0 && a > 0 && rc < ra) continue;  // (a,0,-a): partner is (rc, rb, ra)
+              const int64_t nt = T.ntri[(size_t(ra - 1) * nr + (rb - 1)) * nr + (rc - 1)];
+              if (nt <= 0) continue;
+              const int rs[3] = {ra, rb, rc};
+              double q[3];
+              for (int s = 0; s < 3; ++s) {
+                const double kk = T.mean_radius[rs[s] - 1];
+                q[s] = kk * kk + double(n_s[s]) * double(n_s[s]);
+              }
+              double qs[3] = {q[0], q[1], q[2]};
+              std::sort(qs, qs + 3, [](double x, double y) { return x > y; });
+              const double k1 = std::sqrt(qs[0]);
+              const double k2 = std::sqrt(qs[1]);
+              const double tt = k2 / k1;
+              double mu = ((qs[0] + qs[1]) - qs[2]) / ((2.0 * k1) * k2);
+              mu = std::min(std::max(mu, -1.0), 1.0);
+              if (!(k1 >= b.k1_min && k1 < b.k1_max && tt >= 0.5 && tt <= 1.0 && mu >= 0.5 && mu <= 1.0)) continue;
+              int ik = int(std::floor((k1 - b.k1_min) / dk));
+              ik = std::min(ik, b.n_k1 - 1);
+              int imu = int(std::floor((mu - 0.5) / dmu));
+              imu = std::min(imu, b.n_mu - 1);
+              int it = int(std::floor((tt - 0.5) / dt));
+              it = std::min(it, b.n_t - 1);
+              const int bin = (ik * b.n_mu + imu) * b.n_t + it;
+
+              // orientation weights, averaged over labellings consistent with k1 >= k2 >= k3
+              static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+              double wsum[64], dsum[64];
+              std::fill(wsum, wsum + nlm, 0.0);
+              std::fill(dsum, dsum + nlm, 0.0);
+              int nlab = 0;
+              const double s = std::sqrt(1.0 - mu * mu);
+              const bool degenerate = s < kDegenerateS;
+              for (const auto& p : perms) {
+                if (!(q[p[0]] >= q[p[1]] && q[p[1]] >= q[p[2]])) continue;
+                ++nlab;
+                const double mu1 = double(n_s[p[0]]) / k1;
+                const double mu2 = double(n_s[p[1]]) / k2;
+                double phi = 0.0;
+                if (!degenerate) {
+                  const double px = (mu2 + mu * mu1) / s;
+                  const double py = std::sqrt(std::max((1.0 - mu1 * mu1) - px * px, 0.0));
+                  phi = std::atan2(py, px);
+                }
+                legendre_table(b.l_max, mu1, &P);
+                for (int j = 0; j < nlm; ++j) {
+                  const int l = T.lm_l[j], m = T.lm_m[j];
+                  const double y = nlm_norm[j] * P[l * (b.l_max + 1) + m];
+                  const double w = degenerate ? (m == 0 ? y : 0.0) : y * std::cos(double(m) * phi);
+                  wsum[j] += w;
+                  dsum[j] += y * y;
+                }
+              }
+              ComboRec cr;
+              cr.pt = int32_t(ip);
+              cr.ra = ra;
+              cr.rb = rb;
+              cr.rc = rc;
+              cr.bin = bin;
+              cr.ntri = nt;
+              const bool self_partner = (a == 0) || (bb == 0 && ra == rc);
+              cr.mult = self_partner ? 1 : 2;
+              per_pt[ip].push_back(cr);
+              for (int j = 0; j < nlm; ++j) {
+                per_pt_w[ip].push_back(wsum[j] / double(nlab));
+                per_pt_d[ip].push_back(dsum[j] / double(nlab));
+              }
+              per_pt_kmt[ip].push_back(k1);
+              per_pt_kmt[ip].push_back(mu);
+              per_pt_kmt[ip].push_back(tt);
+            }
+          }
+        }
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+
+  // ---- per-bin geometry sums (den, counts, means) in a fixed order
+  T.bin_count.assign(n_bins, 0);
+  T.bin_den.assign(size_t(nlm) * n_bins, 0.0);
+  std::vector<double> mean_acc(size_t(n_bins) * 3, 0.0), mean_w(n_bins, 0.0);
+  int64_t total = 0;
+  for (size_t ip = 0; ip < pts.size(); ++ip) {
+    if (!per_pt[ip].empty()) T.n_canonical_planes += 1;
+    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
+      const ComboRec& cr = per_pt[ip][i];
+      const double wgt = double(cr.mult) * double(cr.ntri);
+      T.bin_count[cr.bin] += int64_t(cr.mult) * cr.ntri;
+      for (int j = 0; j < nlm; ++j) T.bin_den[size_t(j) * n_bins + cr.bin] += wgt * per_pt_d[ip][i * nlm + j];
+      for (int k = 0; k < 3; ++k) mean_acc[size_t(cr.bin) * 3 + k] += wgt * per_pt_kmt[ip][i * 3 + k];
+      mean_w[cr.bin] += wgt;
+      ++total;
+    }
+  }
+  T.n_combos = total;
+  T.bin_mean.assign(size_t(n_bins) * 3, std::nan(""));
+  for (int i = 0; i < n_bins; ++i)
+    if (mean_w[i] > 0)
+      for (int k = 0; k < 3; ++k) T.bin_mean[size_t(i) * 3 + k] = mean_acc[size_t(i) * 3 + k] / mean_w[i];
+  T.bin_empty_lm.assign(size_t(nlm) * n_bins, 0);
+  for (int j = 0; j < nlm; ++j)
+    for (int i = 0; i < n_bins; ++i)
+      T.bin_empty_lm[size_t(j) * n_bins + i] = (T.bin_count[i] == 0 || T.bin_den[size_t(j) * n_bins + i] == 0.0);
+
+  // ---- K3 work items.  Pairs are (slot A ring, slot C ring); the N dimension
+  // is the slot-B ring.  For every pair the kept slot-B rings are cut into
+  // windows of kTileN consecutive rings; windows are packed greedily into
+  // items of up to kPairsPerItem pairs sharing one window.
+  std::vector<int64_t> combo_item_slot;  // per combination in (pt, enumeration) order
+  combo_item_slot.reserve(total);
+  std::vector<std::vector<int64_t>> pt_combo_slot(pts.size());
+  for (size_t ip = 0; ip < pts.size(); ++ip) {
+    auto& recs = per_pt[ip];
+    if (recs.empty()) continue;
+    const int a = pts[ip].a, bb = pts[ip].b, c = a + bb;
+    // segments: (ra, rc, window start) -> list of combo indices
+    struct Seg {
+      int ra, rc, lo, hi;
+      std::vector<int> idx;
+    };
+    std::map<std::pair<int, int>, std::vector<int>> by_pair;
+    for (int i = 0; i < int(recs.size()); ++i) by_pair[{recs[i].ra, recs[i].rc}].push_back(i);
+    std::vector<Seg> segs;
+    for (auto& kv : by_pair) {
+      auto& v = kv.second;
+      std::sort(v.begin(), v.end(), [&](int x, int y) { return recs[x].rb < recs[y].rb; });
+      size_t p = 0;
+      while (p < v.size()) {
+        Seg sg;
+        sg.ra = kv.first.first;
+        sg.rc = kv.first.second;
+        sg.lo = recs[v[p]].rb;
+        while (p < v.size() && recs[v[p]].rb < sg.lo + kTileN) sg.idx.push_back(v[p++]);
+        sg.hi = recs[sg.idx.back()].rb;
+        segs.push_back(std::move(sg));
+      }
+    }
+    std::sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
+      return x.lo != y.lo ? x.lo < y.lo : (x.hi != y.hi ? x.hi < y.hi : (x.ra != y.ra ? x.ra < y.ra : x.rc < y.rc));
+    });
+    // greedy packing into items
+    struct Item {
+      int lo;
+      std::vector<int> segs;
+    };
+    std::vector<Item> its;
+    for (int s = 0; s < int(segs.size()); ++s) {
+      if (its.empty() || int(its.back().segs.size()) == kPairsPerItem || segs[s].hi >= its.back().lo + kTileN)
+        its.push_back({segs[s].lo, {}});
+      its.back().segs.push_back(s);
+    }
+    // groups of kItemsPerGroup items; each group stages the sides its items use
+    std::vector<int64_t> slot_of(recs.size(), -1);
+    for (size_t g0 = 0; g0 < its.size(); g0 += kItemsPerGroup) {
+      const size_t g1 = std::min(its.size(), g0 + kItemsPerGroup);
+      GroupDesc gd{};
+      gd.side_begin = int32_t(T.group_sides.size());
+      gd.item_begin = int32_t(T.items.size());
+      gd.n_items = int32_t(g1 - g0);
+      gd.conj_mask = (c > 0 ? 4 : 0);  // slot C is plane -(a+b) < 0 unless (0,0,0)
+      std::map<int32_t, int> lds;  // side index -> slot
+      auto slot = [&](int32_t sidx) -> uint8_t {
+        auto it = lds.find(sidx);
+        if (it != lds.end()) return uint8_t(it->second);
+        const int k = int(lds.size());
+        lds[sidx] = k;
+        T.group_sides.push_back(sidx);
+        return uint8_t(k);
+      };
+      std::vector<ItemDesc> descs(g1 - g0);
+      std::vector<std::vector<std::pair<int, int>>> pending(g1 - g0);  // (pair row, n-slot) -> fill later
+      for (size_t ii = g0; ii < g1; ++ii) {
+        ItemDesc& d = descs[ii - g0];
+        const Item& it = its[ii];
+        for (int p = 0; p < kPairsPerItem; ++p) {
+          if (p < int(it.segs.size())) {
+            const Seg& sg = segs[it.segs[p]];
+            d.a_slot[p] = slot(side(sg.ra, a));
+            d.c_slot[p] = slot(side(sg.rc, c));
+          }
+        }
+        for (int j = 0; j < kTileN; ++j) {
+          const int rbj = it.lo + j;
+          const int32_t sidx = side(rbj, bb);
+          if (sidx >= 0 && !(a == 0 && bb == 0 && rbj == 1)) d.b_slot[j] = slot(sidx);
+        }
+      }
+      const int zero_slot = int(lds.size());
+      gd.n_sides = zero_slot;
+      if (zero_slot > 255) return "too many sides in one workgroup";
+      for (size_t ii = g0; ii < g1; ++ii) {
+        ItemDesc& d = descs[ii - g0];
+        const Item& it = its[ii];
+        for (int p = int(it.segs.size()); p < kPairsPerItem; ++p) d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
+        for (int j = 0; j < kTileN; ++j) {
+          const int rbj = it.lo + j;
+          const int32_t sidx = side(rbj, bb);
+          if (sidx < 0 || (a == 0 && bb == 0 && rbj == 1)) d.b_slot[j] = uint8_t(zero_slot);
+        }
+        const int64_t item_index = int64_t(T.items.size()) + int64_t(ii - g0);
+        for (int p = 0; p < int(it.segs.size()); ++p) {
+          const Seg& sg = segs[it.segs[p]];
+          for (int ci : sg.idx) slot_of[ci] = item_index * (kPairsPerItem * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
+        }
+        T.dense_terms += double(kPairsPerItem) * kTileN;
+      }
+      T.max_group_sides = std::max(T.max_group_sides, zero_slot + 1);
+      for (auto& d : descs) T.items.push_back(d);
+      T.groups.push_back(gd);
+    }
+    pt_combo_slot[ip] = std::move(slot_of);
+  }
+  T.useful_terms = double(total);
+  const double X = double(ng) * double(ng);
+  T.dense_terms *= X;
+  T.useful_terms *= X;
+
+  // ---- per-combination coefficients, sorted by bin (stable, in pt order)
+  std::vector<std::pair<int32_t, int64_t>> order;  // (bin, running index)
+  order.reserve(total);
+  std::vector<int64_t> flat_slot;
+  std::vector<double> flat_coef;
+  flat_slot.reserve(total);
+  flat_coef.reserve(size_t(total) * nlm);
+  std::vector<int32_t> flat_bin;
+  flat_bin.reserve(total);
+  const double vol = b.box_len * b.box_len * b.box_len;
+  for (size_t ip = 0; ip < pts.size(); ++ip) {
+    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
+      const ComboRec& cr = per_pt[ip][i];
+      flat_bin.push_back(cr.bin);
+      flat_slot.push_back(pt_combo_slot[ip][i]);
+      for (int j = 0; j < nlm; ++j) {
+        const double den = T.bin_den[size_t(j) * n_bins + cr.bin];
+        const double coef = den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den : 0.0;
+        flat_coef.push_back(coef);
+      }
+    }
+  }
+  (void)vol;
+  std::vector<int64_t> perm(total);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return flat_bin[x] < flat_bin[y]; });
+  T.combo_bin.resize(total);
+  T.combo_slot.resize(total);
+  T.combo_coef.resize(size_t(total) * nlm);
+  T.bin_ptr.assign(n_bins + 1, 0);
+  for (int64_t i = 0; i < total; ++i) {
+    const int64_t src = perm[i];
+    T.combo_bin[i] = flat_bin[src];
+    T.combo_slot[i] = flat_slot[src];
+    for (int j = 0; j < nlm; ++j) T.combo_coef[size_t(i) * nlm + j] = flat_coef[size_t(src) * nlm + j];
+    T.bin_ptr[flat_bin[src] + 1] += 1;
+  }
+  for (int i = 0; i < n_bins; ++i) T.bin_ptr[i + 1] += T.bin_ptr[i];
+  return "";
+}
+
+}  // namespace bk

@@ -1,0 +1,90 @@
+// Host-side geometry and work decomposition of the bispectrum-multipole
+// estimator (arXiv:2405.14513, Sec. II).  Pure C++ (no HIP): built with
+// -ffp-contract=off so every float64 decision that picks an integer (a bin,
+// a kept combination) is taken in plain IEEE operations in a fixed order.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace bk {
+
+struct Binning {
+  int ng = 0;
+  double box_len = 0.0;  // L
+  int n_k1 = 0;
+  double k1_min = 0.0, k1_max = 0.0;
+  int n_mu = 0, n_t = 0;
+  int l_max = 6, m_max = 6;
+};
+
+// Sizes of the K3 work decomposition.
+constexpr int kTileN = 16;        // third-slot rings per work item (MFMA N)
+constexpr int kPairsPerItem = 32;  // ring pairs per work item (two 16-row MFMA tiles)
+constexpr int kItemsPerGroup = 8;  // work items (waves) per workgroup, all on one plane triple
+constexpr int kChunk = 32;         // x_perp points staged in LDS per step
+
+// One workgroup of the contraction kernel: a canonical plane triple and up to
+// kItemsPerGroup work items that share the sides staged in LDS.
+struct GroupDesc {
+  int32_t side_begin;  // into group_sides
+  int32_t n_sides;     // sides staged (the last LDS slot, n_sides, is all zeros)
+  int32_t item_begin;  // first work item
+  int32_t n_items;
+  int32_t conj_mask;   // bit s set: slot s (0 = A, 1 = B, 2 = C) is a negative plane -> conjugate D
+  int32_t pad[3];
+};
+
+// One work item: kPairsPerItem pairs of (slot A ring, slot C ring) and kTileN
+// slot-B rings.  Indices are LDS slots of the owning group.
+struct ItemDesc {
+  uint8_t a_slot[kPairsPerItem];
+  uint8_t c_slot[kPairsPerItem];
+  uint8_t b_slot[kTileN];
+};
+
+struct Tables {
+  Binning bin;
+  int ng = 0, nr = 0, nmax = 0;
+  std::vector<int64_t> edge3;              // 3 * R_r (R_r rational with denominator 3), r = 0..nr
+  std::vector<double> mean_radius;         // K_r, r = 1..nr (index r-1)
+  std::vector<int64_t> ring_count;         // modes per ring
+  std::vector<int64_t> ntri;               // N_tri[r1][r2][r3], nr^3
+  std::vector<int32_t> mode_ring;          // ring (1-based, 0 = none) of every (ux, uy) in [-lim, lim]^2
+  int lim = 0;
+
+  // sides with n >= 0 (the stored ones); side (r, n) -> index or -1
+  std::vector<int32_t> side_of;  // [(nmax+1) * (nr+1)]
+  std::vector<int32_t> side_ring, side_plane;
+
+  // (l, m) outputs
+  std::vector<int> lm_l, lm_m;
+
+  // kept canonical combinations
+  int64_t n_combos = 0;
+  int64_t n_canonical_planes = 0;
+  std::vector<int32_t> combo_bin;        // per combination
+  std::vector<int64_t> combo_slot;       // index into the K3 output (item * 512 + pair * 16 + col)
+  std::vector<double> combo_coef;        // [combo][n_lm]: final coefficient on Re S
+  std::vector<int64_t> bin_ptr;          // combinations sorted by bin: CSR offsets [n_bins + 1]
+  std::vector<int64_t> bin_count;        // sum of mult * N_tri per bin
+  std::vector<double> bin_den;           // [n_lm][n_bins]
+  std::vector<double> bin_mean;          // [n_bins][3]
+  std::vector<uint8_t> bin_empty_lm;     // [n_lm][n_bins] 1 if NaN
+
+  // K3 decomposition
+  std::vector<GroupDesc> groups;
+  std::vector<ItemDesc> items;
+  std::vector<int32_t> group_sides;      // side index per LDS slot
+  int max_group_sides = 0;
+  double dense_terms = 0.0, useful_terms = 0.0;
+};
+
+// Builds everything; returns "" on success or an error message.
+std::string build_tables(const Binning& b, int n_threads, Tables* out);
+
+// Number of (l, m) outputs for l_max, m_max (even l only).
+int count_lm(int l_max, int m_max);
+
+}  // namespace bk
