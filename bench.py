@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Benchmark of the bispectrum-multipole estimator on one MI355X.
+
+Metric: (k1, mu, t) bins x (l, m) multipoles estimated per second for one
+N_g = 256 field (40 k1 x 20 mu x 10 t bins, 16 multipoles = 128 000 values per
+estimate), float32 path; the float64 path is timed beside it for the
+FP32/FP64 speedup.  One step = one complete estimate (forward FFT, ring FFTs,
+triple products, binning) of a field already resident in HBM.
+
+Prints ONE JSON line.  Extra keys: per-stage times, the float64 path, the
+roofline of the dominant kernel (the triple-product contraction), the
+float64 CPU oracle timed on a bounded sample, and the error per multipole
+against stored oracle values when they exist.
+
+  python bench.py [--steps K] [--warmup W] [--ng 256|128] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "triangle bins x (l,m) estimated/sec at N_g=256; FP32-batched vs FP64 speedup"
+PEAK_FP32_MFMA_TFLOPS = 157.3  # MI355X dense FP32 matrix
+PEAK_FP64_TFLOPS = 78.6
+WORKLOADS = {
+    256: dict(n_k1=40, k1_min=1.0, k1_max=256 / 3, n_mu=20, n_t=10),
+    128: dict(n_k1=20, k1_min=1.0, k1_max=128 / 3, n_mu=10, n_t=10),
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("bk_kernels.hpp", "bk_fft.hpp", "bk_tables.cpp", "bk_api.hip"):
+        with open(os.path.join(ROOT, "paper_2405_14513_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(ng):
+    """HBM bytes per K3 launch from a committed rocprofv3 --pmc summary, or None
+    if absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k3_contract_traffic_ng{ng}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_path(bk, torch, binning, prec, field, steps, warmup):
+    est = bk.Estimator(binning, prec=prec)
+    stream = torch.cuda.current_stream().cuda_stream
+    est.load(field, stream)
+    for _ in range(warmup):
+        est.estimate(stream)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    stages = []
+    start.record()
+    for _ in range(steps):
+        est.estimate(stream)
+        stages.append(est.stage_times())  # hipEvents recorded on this stream around each stage
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    B = est.multipoles()[0]
+    info = est.info()
+    est.close()
+    return ms, stages, B, info
+
+
+def cpu_baseline(delta64, ng, wl, info):
+    """The float64 oracle on every m-th plane triple, projected to one estimate."""
+    import numpy as np
+
+    from oracle.estimator import stream_plane_triples
+    from oracle.geometry import Binning, make_rings, make_sides, plane_triples, triangle_counts
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    b = Binning(ng, wl["n_k1"], wl["k1_min"], wl["k1_max"], wl["n_mu"], wl["n_t"])
+    stride = 97 if ng >= 256 else 23
+    t0 = time.perf_counter()
+    rings = make_rings(ng)
+    ntri = triangle_counts(rings)
+    sides = make_sides(rings, b)
+    t_setup = time.perf_counter() - t0
+    triples = plane_triples(int(np.ceil(b.k1_max)))
+    sample = triples[::stride]
+    t0 = time.perf_counter()
+    _, _, _, n_visited = stream_plane_triples(delta64, b, rings, ntri, sides, sample)
+    t_sample = time.perf_counter() - t0
+    total = 2 * info["combinations"] - info["self_partnered"]  # the oracle visits both n -> -n partners
+    t_full = t_setup + t_sample * total / max(n_visited, 1)
+    n_values = b.n_bins * len(b.lms())
+    return {
+        "value": n_values / t_full,
+        "unit": "bin-multipoles/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"float64 oracle (numpy FFT + BLAS contraction) on every {stride}th of {len(triples)} plane "
+                   f"triples: {n_visited} of {int(total)} combinations in {t_sample:.1f} s, plus {t_setup:.1f} s "
+                   f"of ring/N_tri setup; projected full estimate {t_full:.0f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ng", type=int, default=256, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this estimator build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2405_14513_amd import bk
+    from synth import FieldRecipe, field_digest, make_field
+
+    ng = args.ng
+    wl = WORKLOADS[ng]
+    binning = bk.make_binning(ng, wl["n_k1"], wl["k1_min"], wl["k1_max"], wl["n_mu"], wl["n_t"])
+    recipe = FieldRecipe(ng, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)
+    delta64 = make_field(recipe)
+    digest = field_digest(delta64)
+    f32 = torch.from_numpy(delta64.astype(np.float32)).cuda()
+    f64 = torch.from_numpy(delta64).cuda()
+
+    ms32, st32, B32, info = time_path(bk, torch, binning, bk.BK_F32, f32, args.steps, args.warmup)
+    n_values = wl["n_k1"] * wl["n_mu"] * wl["n_t"] * 16
+    out = {
+        "metric": METRIC,
+        "value": n_values / (ms32 * 1e-3),
+        "unit": "bin-multipoles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"N_g={ng} periodic box (cell 1), field g + 0.5 (g^2 - <g^2>) with P ~ k^-2 and Kaiser "
+                         f"beta 0.5 along z, seed 0; {wl['n_k1']} linear k1 shells on [1, N_g/3), "
+                         f"{wl['n_mu']} mu x {wl['n_t']} t bins, 16 multipoles l <= 6, m <= 6"),
+            "ng": ng,
+            "bins": [wl["n_k1"], wl["n_mu"], wl["n_t"]],
+            "n_lm": 16,
+            "fields_per_step": 1,
+            "input": "float32 grid resident in HBM",
+        },
+    }
+    stage_names = ["fft3d", "ring_fft", "triple_products", "binning"]
+    k3_ms = float(np.mean([s[2] for s in st32]))
+    out["stage_ms"] = {k: float(np.mean([s[i] for s in st32])) for i, k in enumerate(stage_names)}
+    flops = info["useful_terms"] * 4.0  # Re(D_A D_C D_B): 2 FMAs per (combination, x_perp) with D_A D_C reused
+    achieved = flops / (k3_ms * 1e-3) / 1e12
+    traffic = read_traffic(ng)
+    out["roofline"] = {
+        "kernel": "k3_contract_kernel<float>",
+        "bound": "mfma",
+        "achieved": achieved,
+        "peak": PEAK_FP32_MFMA_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+        "traffic": traffic,
+        "algorithmic_flops_per_launch": flops,
+        "dense_flops_per_launch": info["dense_terms"] * 4.0,
+        "avg_launch_ms": k3_ms,
+    }
+    out["plan"] = {k: info[k] for k in ("combinations", "work_items", "sides", "rings", "plane_triples")}
+    if not args.no_fp64:
+        ms64, st64, B64, _ = time_path(bk, torch, binning, bk.BK_F64, f64, args.steps, args.warmup)
+        out["fp64"] = {
+            "ms_per_step": ms64,
+            "value": n_values / (ms64 * 1e-3),
+            "stage_ms": {k: float(np.mean([s[i] for s in st64])) for i, k in enumerate(stage_names)},
+        }
+        out["fp32_vs_fp64_speedup"] = ms64 / ms32
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_ng{ng}.npz")
+    if os.path.exists(gold):
+        g = np.load(gold)
+        if str(g["digest"]) == digest:
+            ref = g["B"].reshape(16, -1)
+            errs = {}
+            for name, B in (("f32", B32), ("f64", B64 if not args.no_fp64 else None)):
+                if B is None:
+                    continue
+                Bf = B.reshape(16, -1)
+                ok = ~np.isnan(ref)
+                e = [float(np.max(np.abs(Bf[j][ok[j]] - ref[j][ok[j]])) / np.max(np.abs(ref[j][ok[j]])))
+                     for j in range(16)]
+                errs[name] = e
+            out["error_per_multipole_vs_oracle"] = errs
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
+        del x, y
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(delta64, ng, wl, info)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

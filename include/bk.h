@@ -112,9 +112,10 @@ bk_status bk_get_triangle_counts(bk_plan plan, int64_t* out, size_t cap);
 /* N_tri-weighted mean (k1, mu, t) of each bin, float64 [n_bins][3]; NaN if empty. */
 bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
 
-/* Plan statistics, float64 [8]: combinations, work items, sides, rings,
- * dense products per field (contraction terms incl. padding), useful products,
- * device bytes held, number of canonical plane triples. */
+/* Plan statistics, float64 [9]: combinations (an n -> -n partner pair counted
+ * once), work items, sides, rings, dense products per field (contraction
+ * terms incl. padding), useful products, device bytes held, number of
+ * canonical plane triples, combinations that are their own partner. */
 bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
 
 /* Device time of each stage of the last estimate in milliseconds, float64 [4]:
@@ -131,9 +132,11 @@ bk_status bk_count_triangles(const bk_binning* binning, int64_t* out, size_t cap
  * host memory.  which = 0: Delta planes, complex [batch][nkeep][N][N] (scaled
  * by N^-3/2, planes n = 0..nkeep-1, indices u mod N); 1: D of the stored sides
  * n >= 0, complex [batch][n_sides][N][N] (x_perp index x * N + y); 2: the
- * side table, int32 [n_sides][2] = (ring, n).  Elements are float32 pairs for
- * BK_F32 plans, float64 pairs for BK_F64.  *needed receives the size in bytes;
- * BK_ERR_SIZE if cap_bytes is smaller. */
+ * side table, int32 [n_sides][2] = (ring, n); 3, 4, 5: the contraction's work
+ * items, workgroups and staged-side lists as stored on the host (raw bytes).
+ * Elements of 0 and 1 are float32 pairs for BK_F32 plans, float64 pairs for
+ * BK_F64.  *needed receives the size in bytes; BK_ERR_SIZE if cap_bytes is
+ * smaller.  Buffers 2-5 do not need a device. */
 bk_status bk_debug_get_buffer(bk_plan plan, int which, void* out, size_t cap_bytes, size_t* needed);
 
 /* Test support: runs one 16x16x4 MFMA of the given precision (BK_F32 or BK_F64)

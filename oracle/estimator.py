@@ -183,3 +183,79 @@ def estimate(delta: np.ndarray, binning: Binning, method: str = "fft", geom: Geo
     else:
         raise ValueError(method)
     return multipoles(geom, T)
+
+
+def _stream_chunk(task):
+    """Worker: Eq. 8 sums and Eq. 13 accumulators for one set of plane triples."""
+    delta, binning, rings, ntri, sides, triples = task
+    num, den, counts, _ = stream_plane_triples(delta, binning, rings, ntri, sides, triples)
+    return num, den, counts
+
+
+def stream_plane_triples(delta, binning, rings, ntri, sides, triples):
+    """Eq. 8 sums and Eq. 13 accumulators (num, den, counts) over the given
+    plane triples, plus the number of combinations visited."""
+    from .geometry import Combos, Geometry, combos_for_planes
+
+    n_visited = 0
+    nb = binning.n_bins
+    nlm = len(binning.lms())
+    num = np.zeros((nlm, nb), dtype=np.complex128)
+    den = np.zeros((nlm, nb))
+    counts = np.zeros(nb, dtype=np.int64)
+    Delta = fourier_field(delta, binning.box_len)
+    for pt in triples:
+        res = combos_for_planes(rings, ntri, sides, binning, *pt)
+        if res is None:
+            continue
+        combos = Combos(*res)
+        n_visited += len(combos.ntri)
+        geom = Geometry(binning, rings, ntri, sides, combos)
+        T = triple_sums_fft(geom, Delta)
+        for j in range(nlm):
+            np.add.at(num[j], combos.bin, combos.w[:, j] * T)
+            np.add.at(den[j], combos.bin, combos.d[:, j] * combos.ntri.astype(np.float64))
+        np.add.at(counts, combos.bin, combos.ntri)
+    return num, den, counts, n_visited
+
+
+def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, chunks: int = 64) -> Multipoles:
+    """Same result as ``estimate`` without holding every combination at once.
+
+    Follows the paper's implementation note (end of Sec. II): the first-level
+    estimates are never stored; each one's contribution to the numerator and
+    denominator of Eq. 13 is accumulated as soon as it is computed.  Plane
+    triples are split into ``chunks`` groups, optionally over ``workers``
+    processes; the partial sums are added in chunk order.
+    """
+    from .geometry import make_rings, make_sides, plane_triples, triangle_counts
+
+    rings = make_rings(binning.ng)
+    ntri = triangle_counts(rings)
+    sides = make_sides(rings, binning)
+    triples = plane_triples(int(math.ceil(binning.k1_max)))
+    groups = [triples[i::chunks] for i in range(chunks)]
+    tasks = [(delta, binning, rings, ntri, sides, g) for g in groups if g]
+    if workers > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_stream_chunk, tasks, chunksize=1)
+    else:
+        parts = [_stream_chunk(t) for t in tasks]
+    nb = binning.n_bins
+    lms = binning.lms()
+    num = np.zeros((len(lms), nb), dtype=np.complex128)
+    den = np.zeros((len(lms), nb))
+    counts = np.zeros(nb, dtype=np.int64)
+    for pnum, pden, pc in parts:
+        num += pnum
+        den += pden
+        counts += pc
+    pref = np.array([math.sqrt((2 * l + 1) / (4.0 * math.pi)) for l, _ in lms])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        B = pref[:, None] * num.real / den
+    B[:, counts == 0] = np.nan
+    B[den == 0.0] = np.nan
+    shape = (len(lms), binning.n_k1, binning.n_mu, binning.n_t)
+    return Multipoles(lms, B.reshape(shape), counts.reshape(shape[1:]), num, den)

@@ -172,10 +172,10 @@ def bk_get_bin_means(plan: int) -> np.ndarray:
 
 
 def bk_get_plan_info(plan: int) -> dict:
-    out = np.empty(8, dtype=np.float64)
-    _check(lib().bk_get_plan_info(ctypes.c_void_p(plan), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 8))
+    out = np.empty(9, dtype=np.float64)
+    _check(lib().bk_get_plan_info(ctypes.c_void_p(plan), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 9))
     keys = ["combinations", "work_items", "sides", "rings", "dense_terms", "useful_terms", "device_bytes",
-            "plane_triples"]
+            "plane_triples", "self_partnered"]
     return dict(zip(keys, out.tolist()))
 
 
@@ -197,8 +197,10 @@ def bk_count_triangles(binning: bk_binning):
 def bk_debug_get_buffer(plan: int, which: int, prec: int) -> np.ndarray:
     need = ctypes.c_size_t()
     _check(lib().bk_debug_get_buffer(ctypes.c_void_p(plan), int(which), None, 0, ctypes.byref(need)))
-    if which == 2:
+    if which in (2, 4, 5):
         out = np.empty(need.value // 4, dtype=np.int32)
+    elif which == 3:
+        out = np.empty(need.value, dtype=np.uint8)
     else:
         out = np.empty(need.value // (8 if prec == BK_F32 else 16), dtype=np.complex64 if prec == BK_F32 else np.complex128)
     _check(lib().bk_debug_get_buffer(ctypes.c_void_p(plan), int(which), ctypes.c_void_p(out.ctypes.data), out.nbytes,

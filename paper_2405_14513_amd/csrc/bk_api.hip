@@ -68,6 +68,7 @@ struct bk_plan_s {
   double norm = 0.0;
   double delta_scale = 1.0;
   size_t lds_k3 = 0;
+  int k3_chunk = 32;
   size_t bytes = 0;
 
   void* d_in = nullptr;       // [max_batch][N^3] of the input dtype
@@ -185,8 +186,13 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
   // K3: triple products
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
-    hipLaunchKernelGGL((bk::k3_contract_kernel<T>), g3, dim3(64 * bk::kItemsPerGroup), p->lds_k3, st, D,
-                       p->n_sides, p->d_groups, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
+    const int ng = int(p->tab.groups.size());
+    if (p->k3_chunk == 64)
+      hipLaunchKernelGGL((bk::k3_contract_kernel<T, 64>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides,
+                         p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
+    else
+      hipLaunchKernelGGL((bk::k3_contract_kernel<T, 32>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides,
+                         p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
     BK_HIP(hipGetLastError());
   }
   BK_HIP(hipEventRecord(p->ev[3], st));
@@ -293,6 +299,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   bk::Tables& T = p->tab;
   const int n = bn->ng;
   p->X = long(n) * n;
+  const long X_ = p->X;
   p->nkeep = T.nmax + 1;
   if (p->nkeep > n / 2 + 1) p->nkeep = n / 2 + 1;
   p->n_sides = long(T.side_ring.size());
@@ -371,11 +378,25 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   std::vector<double>().swap(T.combo_coef);
   std::vector<int64_t>().swap(T.combo_slot);
 
-  p->lds_k3 = size_t(T.max_group_sides) * bk::kLdsStride * cs;
-  if (p->lds_k3 > 65536) {
-    release(p);
-    delete p;
-    return fail(BK_ERR_ARG, "workgroup staging exceeds 64 KiB of LDS");
+  {
+    // largest chunk whose staging fits 64 KiB of LDS and the per-thread load budget
+    p->k3_chunk = 0;
+    for (int ch : {64, 32}) {
+      if (X_ % ch != 0) continue;
+      const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
+      const size_t lds = size_t(T.max_group_sides) * slot;
+      const long loads = long(T.max_group_sides - 1) * (ch / int(16 / cs));
+      if (lds <= 65536 && loads <= long(bk::kK3MaxLoads) * bk::kK3Threads) {
+        p->k3_chunk = ch;
+        p->lds_k3 = lds;
+        break;
+      }
+    }
+    if (p->k3_chunk == 0) {
+      release(p);
+      delete p;
+      return fail(BK_ERR_ARG, "workgroup staging exceeds 64 KiB of LDS or the per-thread load budget");
+    }
   }
   for (auto& e : p->ev) {
     hipError_t he = hipEventCreate(&e);
@@ -496,7 +517,7 @@ bk_status bk_get_bin_means(bk_plan p, double* out, size_t cap) {
 bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
   g_last_error.clear();
   if (!p || !info) return fail(BK_ERR_ARG, "null argument");
-  if (cap < 8) return fail(BK_ERR_SIZE, "info buffer needs 8 entries");
+  if (cap < 9) return fail(BK_ERR_SIZE, "info buffer needs 9 entries");
   info[0] = double(p->tab.n_combos);
   info[1] = double(p->n_items);
   info[2] = double(p->n_sides);
@@ -505,6 +526,7 @@ bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
   info[5] = p->tab.useful_terms;
   info[6] = double(p->bytes);
   info[7] = double(p->tab.n_canonical_planes);
+  info[8] = double(p->tab.n_self_partner);
   return BK_OK;
 }
 
@@ -543,14 +565,27 @@ bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes,
       table.push_back(p->tab.side_plane[s]);
     }
     bytes = table.size() * sizeof(int32_t);
+  } else if (which == 3) {
+    bytes = p->tab.items.size() * sizeof(bk::ItemDesc);
+  } else if (which == 4) {
+    bytes = p->tab.groups.size() * sizeof(bk::GroupDesc);
+  } else if (which == 5) {
+    bytes = p->tab.group_sides.size() * sizeof(int32_t);
   } else {
-    return fail(BK_ERR_ARG, "which must be 0, 1 or 2");
+    return fail(BK_ERR_ARG, "which must be 0..5");
   }
   if (needed) *needed = bytes;
   if (!out) return BK_OK;
   if (cap_bytes < bytes) return fail(BK_ERR_SIZE, "output buffer too small");
   if (which == 2) {
     std::memcpy(out, table.data(), bytes);
+    return BK_OK;
+  }
+  if (which >= 3) {
+    const void* hs = which == 3 ? static_cast<const void*>(p->tab.items.data())
+                     : which == 4 ? static_cast<const void*>(p->tab.groups.data())
+                                  : static_cast<const void*>(p->tab.group_sides.data());
+    std::memcpy(out, hs, bytes);
     return BK_OK;
   }
   if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run");

@@ -12,7 +12,7 @@
 namespace bk {
 
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {
   T x, y;
 };
 

@@ -194,23 +194,52 @@ struct Mfma<double> {
   static __device__ __forceinline__ int out_row(int kq, int k) { return 4 * k + kq; }
 };
 
-constexpr int kLdsStride = kChunk + 1;  // complex elements per LDS slot (padded)
+// LDS slot stride in complex elements: an odd number of 8-byte words between
+// slots so the 16 rows of an MFMA tile, reading 16 different slots at one
+// point, fall in different banks.
+//
+// float32: slot = CH interleaved complex values (8-byte reads), stride CH + 1.
+// float64: slot = CH real parts then CH imaginary parts (two 8-byte reads per
+// value instead of one 16-byte read), stride 2 CH + 1 doubles.
+template <typename T, int CH>
+struct K3Lds {
+  static constexpr bool split = sizeof(T) == 8;
+  static constexpr int stride = split ? 2 * CH + 1 : CH + 1;     // in units of T (split) or complex
+  static constexpr int vec = 16 / int(sizeof(cplx<T>));          // complex per 16-byte global load
+  static constexpr int per_side = CH / vec;                      // 16-byte loads per side per chunk
+  static constexpr size_t slot_bytes = split ? size_t(stride) * sizeof(T) : size_t(stride) * sizeof(cplx<T>);
+};
 constexpr int kItemOut = kPairsPerItem * kTileN;
+constexpr int kK3Threads = 64 * kItemsPerGroup;
+constexpr int kK3MaxLoads = 8;  // 16-byte global loads per thread per chunk
 
 // One block = one GroupDesc (all on one canonical plane triple), one wave per
-// work item.  Every kChunk points of x_perp the block stages the group's sides
-// into LDS; each wave then forms the pair products P = D_A D_C (4 points per
-// lane group) and feeds Re P, Im P against Re D_B, -Im D_B into 16x16x4 MFMAs
-// (K = 4 points).  Partial sums of one chunk are added to float64 registers.
-template <typename T>
-__global__ __launch_bounds__(512) void k3_contract_kernel(const cplx<T>* __restrict__ D, long n_sides_total,
-                                                          const GroupDesc* __restrict__ groups,
-                                                          const ItemDesc* __restrict__ items,
-                                                          const int32_t* __restrict__ group_sides, long X,
-                                                          double* __restrict__ S_out, long n_items_total) {
+// work item.  Every CH points of x_perp the block stages the group's sides
+// into LDS (16-byte loads, the next chunk prefetched into registers while the
+// current one is consumed); each wave then forms the pair products
+// P = D_A D_C (4 points per lane group) and feeds Re P, Im P against Re D_B,
+// -Im D_B into 16x16x4 MFMAs (K = 4 points).  The chunk's partial sums are
+// added to float64 registers.  Blocks are visited XCD by XCD: consecutive
+// block ids go to different XCDs, so block id q*8 + x runs group
+// x*ceil(G/8) + q and each XCD's L2 serves consecutive groups, which share
+// plane triples.
+template <typename T, int CH>
+__global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long n_sides_total,
+                                                                 const GroupDesc* __restrict__ groups, int n_groups,
+                                                                 const ItemDesc* __restrict__ items,
+                                                                 const int32_t* __restrict__ group_sides, long X,
+                                                                 double* __restrict__ S_out, long n_items_total) {
+  using L = K3Lds<T, CH>;
+  typedef uint4 v16;
   extern __shared__ char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const GroupDesc gd = groups[blockIdx.x];
+  int gid;
+  {
+    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;
+    const int Q = n_groups >> 3, R = n_groups & 7;
+    gid = xcd < R ? xcd * (Q + 1) + q : R * (Q + 1) + (xcd - R) * Q + q;
+  }
+  const GroupDesc gd = groups[gid];
   const int b = blockIdx.y;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -218,50 +247,98 @@ __global__ __launch_bounds__(512) void k3_contract_kernel(const cplx<T>* __restr
   const int kq = lane >> 4;
   const cplx<T>* Db = D + size_t(b) * n_sides_total * X;
 
+  T* ldsr = reinterpret_cast<T*>(smem_raw);  // split layout view
   // zero slot
-  for (int i = threadIdx.x; i < kLdsStride; i += blockDim.x) lds[gd.n_sides * kLdsStride + i] = {T(0), T(0)};
+  if constexpr (L::split) {
+    for (int i = threadIdx.x; i < L::stride; i += blockDim.x) ldsr[gd.n_sides * L::stride + i] = T(0);
+  } else {
+    for (int i = threadIdx.x; i < L::stride; i += blockDim.x) lds[gd.n_sides * L::stride + i] = {T(0), T(0)};
+  }
+
+  // this thread's staging loads: global source and LDS destination per chunk
+  const v16* src[kK3MaxLoads];
+  int dst[kK3MaxLoads];
+  const int n_loads = gd.n_sides * L::per_side;
+#pragma unroll
+  for (int i = 0; i < kK3MaxLoads; ++i) {
+    const int q = threadIdx.x + i * kK3Threads;
+    const int qq = q < n_loads ? q : 0;
+    const int sl = qq / L::per_side, v = qq - sl * L::per_side;
+    src[i] = reinterpret_cast<const v16*>(Db + size_t(group_sides[gd.side_begin + sl]) * X + v * L::vec);
+    dst[i] = sl * L::stride + v * L::vec;
+  }
+  v16 stage[kK3MaxLoads];
+#pragma unroll
+  for (int i = 0; i < kK3MaxLoads; ++i)
+    if (threadIdx.x + i * kK3Threads < n_loads) stage[i] = src[i][0];
 
   const bool active = wave < gd.n_items;
   int sa0 = 0, sc0 = 0, sa1 = 0, sc1 = 0, sb = 0;
   if (active) {
     const ItemDesc& it = items[gd.item_begin + wave];
-    sa0 = it.a_slot[row];
-    sc0 = it.c_slot[row];
-    sa1 = it.a_slot[16 + row];
-    sc1 = it.c_slot[16 + row];
-    sb = it.b_slot[row];
+    sa0 = it.a_slot[row] * L::stride;
+    sc0 = it.c_slot[row] * L::stride;
+    sa1 = it.a_slot[16 + row] * L::stride;
+    sc1 = it.c_slot[16 + row] * L::stride;
+    sb = it.b_slot[row] * L::stride;
   }
-  const T sgnA = (gd.conj_mask & 1) ? T(-1) : T(1);
-  const T sgnB = (gd.conj_mask & 2) ? T(-1) : T(1);
-  const T sgnC = (gd.conj_mask & 4) ? T(-1) : T(1);
-
+  // Slot C always lies on plane -(a+b) <= 0 and is read as conj D(r, a+b); on
+  // the (0,0,0) triple D(r, 0) is real, so the conjugate changes nothing.
   typedef typename Mfma<T>::acc_t acc_t;
   double out0[4] = {0, 0, 0, 0}, out1[4] = {0, 0, 0, 0};
-  const int nstage = gd.n_sides * kChunk;
-  for (long x0 = 0; x0 < X; x0 += kChunk) {
-    __syncthreads();
-    for (int q = threadIdx.x; q < nstage; q += blockDim.x) {
-      const int s = q / kChunk, i = q - s * kChunk;
-      lds[s * kLdsStride + i] = Db[size_t(group_sides[gd.side_begin + s]) * X + x0 + i];
+  const long step = long(CH) / L::vec;  // 16-byte units per chunk
+  for (long x0 = 0; x0 < X; x0 += CH) {
+    __syncthreads();  // previous chunk fully consumed
+#pragma unroll
+    for (int i = 0; i < kK3MaxLoads; ++i) {
+      if (threadIdx.x + i * kK3Threads < n_loads) {
+        // slots are 8-byte aligned only (odd stride): store 8 bytes at a time
+        const cplx<T>* v = reinterpret_cast<const cplx<T>*>(&stage[i]);
+        if constexpr (L::split) {
+          ldsr[dst[i]] = v[0].x;
+          ldsr[dst[i] + CH] = v[0].y;
+        } else {
+#pragma unroll
+          for (int e = 0; e < L::vec; ++e) lds[dst[i] + e] = v[e];
+        }
+      }
     }
     __syncthreads();
+    if (x0 + CH < X) {
+#pragma unroll
+      for (int i = 0; i < kK3MaxLoads; ++i) {
+        if (threadIdx.x + i * kK3Threads < n_loads) {
+          src[i] += step;
+          stage[i] = src[i][0];
+        }
+      }
+    }
     if (active) {
       acc_t r0 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
 #pragma unroll
-      for (int ks = 0; ks < kChunk / 4; ++ks) {
+      for (int ks = 0; ks < CH / 4; ++ks) {
         const int xi = ks * 4 + kq;
-        const cplx<T> a0 = lds[sa0 * kLdsStride + xi];
-        const cplx<T> c0 = lds[sc0 * kLdsStride + xi];
-        const cplx<T> a1 = lds[sa1 * kLdsStride + xi];
-        const cplx<T> c1 = lds[sc1 * kLdsStride + xi];
-        const cplx<T> bv = lds[sb * kLdsStride + xi];
-        const cplx<T> p0 = cmul(cplx<T>{a0.x, sgnA * a0.y}, cplx<T>{c0.x, sgnC * c0.y});
-        const cplx<T> p1 = cmul(cplx<T>{a1.x, sgnA * a1.y}, cplx<T>{c1.x, sgnC * c1.y});
-        const T br = bv.x, bi = -sgnB * bv.y;  // Re(P B) = Re P Re B - Im P Im B
-        r0 = Mfma<T>::step(p0.x, br, r0);
-        r1 = Mfma<T>::step(p1.x, br, r1);
-        i0 = Mfma<T>::step(p0.y, bi, i0);
-        i1 = Mfma<T>::step(p1.y, bi, i1);
+        cplx<T> a0, c0, a1, c1, bv;
+        if constexpr (L::split) {
+          a0 = {ldsr[sa0 + xi], ldsr[sa0 + CH + xi]};
+          c0 = {ldsr[sc0 + xi], ldsr[sc0 + CH + xi]};
+          a1 = {ldsr[sa1 + xi], ldsr[sa1 + CH + xi]};
+          c1 = {ldsr[sc1 + xi], ldsr[sc1 + CH + xi]};
+          bv = {ldsr[sb + xi], ldsr[sb + CH + xi]};
+        } else {
+          a0 = lds[sa0 + xi];
+          c0 = lds[sc0 + xi];
+          a1 = lds[sa1 + xi];
+          c1 = lds[sc1 + xi];
+          bv = lds[sb + xi];
+        }
+        // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
+        const T p0r = a0.x * c0.x + a0.y * c0.y, p0n = a0.x * c0.y - a0.y * c0.x;
+        const T p1r = a1.x * c1.x + a1.y * c1.y, p1n = a1.x * c1.y - a1.y * c1.x;
+        r0 = Mfma<T>::step(p0r, bv.x, r0);
+        r1 = Mfma<T>::step(p1r, bv.x, r1);
+        i0 = Mfma<T>::step(p0n, bv.y, i0);
+        i1 = Mfma<T>::step(p1n, bv.y, i1);
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {

@@ -321,6 +321,7 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
       for (int j = 0; j < nlm; ++j) T.bin_den[size_t(j) * n_bins + cr.bin] += wgt * per_pt_d[ip][i * nlm + j];
       for (int k = 0; k < 3; ++k) mean_acc[size_t(cr.bin) * 3 + k] += wgt * per_pt_kmt[ip][i * 3 + k];
       mean_w[cr.bin] += wgt;
+      if (cr.mult == 1) T.n_self_partner += 1;
       ++total;
     }
   }
@@ -389,16 +390,34 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
       gd.side_begin = int32_t(T.group_sides.size());
       gd.item_begin = int32_t(T.items.size());
       gd.n_items = int32_t(g1 - g0);
-      gd.conj_mask = (c > 0 ? 4 : 0);  // slot C is plane -(a+b) < 0 unless (0,0,0)
+      gd.conj_mask = 4;  // slot C is plane -(a+b); D(r, 0) is real, so conj is harmless on (0,0,0)
+      // LDS slots: the group's sides numbered in (plane, ring) order, so rows
+      // of a tile that read different rings of one plane read different banks.
       std::map<int32_t, int> lds;  // side index -> slot
-      auto slot = [&](int32_t sidx) -> uint8_t {
-        auto it = lds.find(sidx);
-        if (it != lds.end()) return uint8_t(it->second);
-        const int k = int(lds.size());
-        lds[sidx] = k;
-        T.group_sides.push_back(sidx);
-        return uint8_t(k);
-      };
+      for (size_t ii = g0; ii < g1; ++ii) {
+        const Item& it = its[ii];
+        for (int p = 0; p < int(it.segs.size()); ++p) {
+          lds[side(segs[it.segs[p]].ra, a)] = 0;
+          lds[side(segs[it.segs[p]].rc, c)] = 0;
+        }
+        for (int j = 0; j < kTileN; ++j) {
+          const int32_t sidx = side(it.lo + j, bb);
+          if (sidx >= 0) lds[sidx] = 0;
+        }
+      }
+      {
+        std::vector<int32_t> order;
+        for (auto& kv : lds) order.push_back(kv.first);
+        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+          return T.side_plane[x] != T.side_plane[y] ? T.side_plane[x] < T.side_plane[y]
+                                                    : T.side_ring[x] < T.side_ring[y];
+        });
+        for (size_t k = 0; k < order.size(); ++k) {
+          lds[order[k]] = int(k);
+          T.group_sides.push_back(order[k]);
+        }
+      }
+      auto slot = [&](int32_t sidx) -> uint8_t { return uint8_t(lds.at(sidx)); };
       std::vector<ItemDesc> descs(g1 - g0);
       std::vector<std::vector<std::pair<int, int>>> pending(g1 - g0);  // (pair row, n-slot) -> fill later
       for (size_t ii = g0; ii < g1; ++ii) {

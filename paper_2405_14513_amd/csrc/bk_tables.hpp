@@ -23,7 +23,7 @@ struct Binning {
 constexpr int kTileN = 16;        // third-slot rings per work item (MFMA N)
 constexpr int kPairsPerItem = 32;  // ring pairs per work item (two 16-row MFMA tiles)
 constexpr int kItemsPerGroup = 8;  // work items (waves) per workgroup, all on one plane triple
-constexpr int kChunk = 32;         // x_perp points staged in LDS per step
+constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
 
 // One workgroup of the contraction kernel: a canonical plane triple and up to
 // kItemsPerGroup work items that share the sides staged in LDS.
@@ -63,6 +63,7 @@ struct Tables {
 
   // kept canonical combinations
   int64_t n_combos = 0;
+  int64_t n_self_partner = 0;             // combinations equal to their n -> -n partner
   int64_t n_canonical_planes = 0;
   std::vector<int32_t> combo_bin;        // per combination
   std::vector<int64_t> combo_slot;       // index into the K3 output (item * 512 + pair * 16 + col)

@@ -1,0 +1,59 @@
+"""Full-size parity: the N_g = 128 and N_g = 256 workloads, in the launch
+configuration bench.py times, against stored float64 oracle values.
+
+tests/golden/oracle_ng<N>.npz was written by tests/golden/make_golden.py,
+which calls only the oracle; the field is regenerated here from its seed and
+checked against the stored SHA-256 before use.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from synth import FieldRecipe, field_digest, make_field
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WORKLOADS = {
+    128: (20, 1.0, 128 / 3, 10, 10),
+    256: (40, 1.0, 256 / 3, 20, 10),
+}
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("ng", [128, 256])
+def test_fullsize_against_stored_oracle(ng, prec):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_14513_amd import bk
+
+    print(f"full-size parity ng={ng} prec={prec}", flush=True)
+    gold = np.load(os.path.join(HERE, "golden", f"oracle_ng{ng}.npz"))
+    delta = make_field(FieldRecipe(ng, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0))
+    assert field_digest(delta) == str(gold["digest"]), "regenerated field differs from the stored one"
+    est = bk.Estimator(bk.make_binning(ng, *WORKLOADS[ng]), prec=prec)
+    try:
+        arr = delta.astype(np.float32) if prec == 1 else delta
+        t = torch.from_numpy(arr).cuda()
+        s = torch.cuda.current_stream().cuda_stream
+        est.load(t, s)
+        est.estimate(s)
+        B = est.multipoles()[0]
+        counts = est.counts()
+        lms = est.lm_list()
+    finally:
+        est.close()
+    assert [tuple(x) for x in gold["lms"].tolist()] == lms
+    assert np.array_equal(counts, gold["counts"])
+    ref = gold["B"]
+    assert np.array_equal(np.isnan(B), np.isnan(ref))
+    nlm = ref.shape[0]
+    Bf, rf = B.reshape(nlm, -1), ref.reshape(nlm, -1)
+    ok = ~np.isnan(rf)
+    err = np.array([np.max(np.abs(Bf[j][ok[j]] - rf[j][ok[j]])) / np.max(np.abs(rf[j][ok[j]])) for j in range(nlm)])
+    print(f"  max error per multipole {err.max():.3e}", flush=True)
+    # float32: input rounded to float32, float32 FFTs and products, float64 sums
+    assert err.max() < (1e-11 if prec == 2 else 1e-5), err
