@@ -222,10 +222,11 @@ def main():
                 errs[name] = e
             out["error_per_multipole_vs_oracle"] = errs
     if args.copy_calibration:
+        # a plain streaming kernel of known size: y = 2 x over 1 GiB reads 1 GiB and writes 1 GiB
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        y.copy_(x)
+        torch.mul(x, 2.0, out=y)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
         del x, y
