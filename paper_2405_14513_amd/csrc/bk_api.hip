@@ -68,6 +68,7 @@ struct bk_plan_s {
   double norm = 0.0;
   double delta_scale = 1.0;
   size_t lds_k3 = 0;
+  int item_out = 512;     // float64 outputs per work item
   int k3_chunk = 32;
   size_t bytes = 0;
 
@@ -187,12 +188,19 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
     const int ng = int(p->tab.groups.size());
-    if (p->k3_chunk == 64)
-      hipLaunchKernelGGL((bk::k3_contract_kernel<T, 64>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides,
-                         p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
+#define BK_K3(CHV, TV)                                                                                          \
+  hipLaunchKernelGGL((bk::k3_contract_kernel<T, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides, \
+                     p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items)
+    const int tiles = p->tab.k3.pairs_per_item / 16;
+    if (p->k3_chunk == 64 && tiles == 2)
+      BK_K3(64, 2);
+    else if (p->k3_chunk == 64)
+      BK_K3(64, 4);
+    else if (tiles == 2)
+      BK_K3(32, 2);
     else
-      hipLaunchKernelGGL((bk::k3_contract_kernel<T, 32>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides,
-                         p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items);
+      BK_K3(32, 4);
+#undef BK_K3
     BK_HIP(hipGetLastError());
   }
   BK_HIP(hipEventRecord(p->ev[3], st));
@@ -200,7 +208,7 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
   {
     const int n_bins = p->tab.bin.n_k1 * p->tab.bin.n_mu * p->tab.bin.n_t;
     dim3 g4(n_bins, B);
-    hipLaunchKernelGGL(bk::k4_bin_kernel, g4, dim3(64), 0, st, p->d_S, p->n_items * long(bk::kItemOut), p->d_bin_ptr,
+    hipLaunchKernelGGL(bk::k4_bin_kernel, g4, dim3(64), 0, st, p->d_S, p->n_items * long(p->item_out), p->d_bin_ptr,
                        p->d_combo_slot, p->d_coef, p->d_empty, int(p->tab.lm_l.size()), n_bins, p->norm, p->d_B);
     BK_HIP(hipGetLastError());
   }
@@ -252,7 +260,7 @@ extern "C" bk_status bk_count_triangles(const bk_binning* bn, int64_t* out, size
   bk::Tables T;
   std::string err;
   try {
-    err = bk::build_tables(b, host_threads(), &T);
+    err = bk::build_tables(b, bk::K3Shape(), host_threads(), &T);
   } catch (const std::bad_alloc&) {
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
   }
@@ -285,9 +293,15 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   p->device = device;
   p->max_batch = max_batch;
   p->sh = sh;
+  // Work-item shape: float32 is MFMA-issue bound and keeps two row tiles per
+  // wave (less padding); float64 moves twice the LDS bytes per MFMA and runs
+  // faster with four tiles sharing each slot-B read.  BK_K3_PAIRS overrides.
+  bk::K3Shape shape;
+  shape.pairs_per_item = prec == BK_F32 ? 32 : 64;
+  if (const char* v = std::getenv("BK_K3_PAIRS")) shape.pairs_per_item = std::atoi(v);
   std::string err;
   try {
-    err = bk::build_tables(b, host_threads(), &p->tab);
+    err = bk::build_tables(b, shape, host_threads(), &p->tab);
   } catch (const std::bad_alloc&) {
     delete p;
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
@@ -304,6 +318,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   if (p->nkeep > n / 2 + 1) p->nkeep = n / 2 + 1;
   p->n_sides = long(T.side_ring.size());
   p->n_items = long(T.items.size());
+  p->item_out = T.k3.pairs_per_item * bk::kTileN;
   p->elem = prec == BK_F32 ? 4 : 8;
   const size_t cs = 2 * p->elem;
   // scale so float32 sums stay far from overflow: Delta' = Delta_DFT / N^{3/2}
@@ -352,7 +367,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(dalloc(p, &p->d_F, size_t(max_batch) * p->nkeep * size_t(n) * n * cs));
   TRY(dalloc(p, &p->d_G, size_t(max_batch) * size_t(p->g_total) * cs));
   TRY(dalloc(p, &p->d_D, size_t(max_batch) * size_t(p->n_sides) * size_t(p->X) * cs));
-  TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * bk::kItemOut * 8));
+  TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * p->item_out * 8));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_B), size_t(max_batch) * nlm * n_bins * 8));
   if (prec == BK_F32)
     TRY(put(p, reinterpret_cast<float**>(&p->d_tw), twf.data(), twf.size()));

@@ -209,30 +209,32 @@ struct K3Lds {
   static constexpr int per_side = CH / vec;                      // 16-byte loads per side per chunk
   static constexpr size_t slot_bytes = split ? size_t(stride) * sizeof(T) : size_t(stride) * sizeof(cplx<T>);
 };
-constexpr int kItemOut = kPairsPerItem * kTileN;
 constexpr int kK3Threads = 64 * kItemsPerGroup;
 constexpr int kK3MaxLoads = 8;  // 16-byte global loads per thread per chunk
 
 // One block = one GroupDesc (all on one canonical plane triple), one wave per
-// work item.  Every CH points of x_perp the block stages the group's sides
-// into LDS (16-byte loads, the next chunk prefetched into registers while the
-// current one is consumed); each wave then forms the pair products
-// P = D_A D_C (4 points per lane group) and feeds Re P, Im P against Re D_B,
-// -Im D_B into 16x16x4 MFMAs (K = 4 points).  The chunk's partial sums are
+// work item of 16 * TILES ring pairs x 16 slot-B rings.  Every CH points of
+// x_perp the block stages the group's sides into LDS (16-byte loads, the next
+// chunk prefetched into registers while the current one is consumed); each
+// wave then forms the pair products P = D_A conj(D_C) (4 points per lane
+// group) and feeds Re P, -Im P against Re D_B, Im D_B into 16x16x4 MFMAs
+// (K = 4 points), one accumulator per row tile.  The chunk's partial sums are
 // added to float64 registers.  Blocks are visited XCD by XCD: consecutive
 // block ids go to different XCDs, so block id q*8 + x runs group
 // x*ceil(G/8) + q and each XCD's L2 serves consecutive groups, which share
 // plane triples.
-template <typename T, int CH>
+template <typename T, int CH, int TILES>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long n_sides_total,
                                                                  const GroupDesc* __restrict__ groups, int n_groups,
                                                                  const ItemDesc* __restrict__ items,
                                                                  const int32_t* __restrict__ group_sides, long X,
                                                                  double* __restrict__ S_out, long n_items_total) {
   using L = K3Lds<T, CH>;
+  constexpr int kOut = 16 * TILES * kTileN;
   typedef uint4 v16;
   extern __shared__ char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  T* ldsr = reinterpret_cast<T*>(smem_raw);  // split layout view
   int gid;
   {
     const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;
@@ -247,7 +249,6 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   const int kq = lane >> 4;
   const cplx<T>* Db = D + size_t(b) * n_sides_total * X;
 
-  T* ldsr = reinterpret_cast<T*>(smem_raw);  // split layout view
   // zero slot
   if constexpr (L::split) {
     for (int i = threadIdx.x; i < L::stride; i += blockDim.x) ldsr[gd.n_sides * L::stride + i] = T(0);
@@ -272,20 +273,28 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   for (int i = 0; i < kK3MaxLoads; ++i)
     if (threadIdx.x + i * kK3Threads < n_loads) stage[i] = src[i][0];
 
-  const bool active = wave < gd.n_items;
-  int sa0 = 0, sc0 = 0, sa1 = 0, sc1 = 0, sb = 0;
-  if (active) {
-    const ItemDesc& it = items[gd.item_begin + wave];
-    sa0 = it.a_slot[row] * L::stride;
-    sc0 = it.c_slot[row] * L::stride;
-    sa1 = it.a_slot[16 + row] * L::stride;
-    sc1 = it.c_slot[16 + row] * L::stride;
-    sb = it.b_slot[row] * L::stride;
-  }
   // Slot C always lies on plane -(a+b) <= 0 and is read as conj D(r, a+b); on
   // the (0,0,0) triple D(r, 0) is real, so the conjugate changes nothing.
+  const bool active = wave < gd.n_items;
+  int sa[TILES], sc[TILES], sb = 0;
+#pragma unroll
+  for (int t = 0; t < TILES; ++t) sa[t] = sc[t] = 0;
+  if (active) {
+    const ItemDesc& it = items[gd.item_begin + wave];
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+      sa[t] = it.a_slot[16 * t + row] * L::stride;
+      sc[t] = it.c_slot[16 * t + row] * L::stride;
+    }
+    sb = it.b_slot[row] * L::stride;
+  }
+
   typedef typename Mfma<T>::acc_t acc_t;
-  double out0[4] = {0, 0, 0, 0}, out1[4] = {0, 0, 0, 0};
+  double out[TILES][4];
+#pragma unroll
+  for (int t = 0; t < TILES; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[t][k] = 0.0;
   const long step = long(CH) / L::vec;  // 16-byte units per chunk
   for (long x0 = 0; x0 < X; x0 += CH) {
     __syncthreads();  // previous chunk fully consumed
@@ -314,47 +323,49 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
       }
     }
     if (active) {
-      acc_t r0 = {0, 0, 0, 0}, i0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, i1 = {0, 0, 0, 0};
+      acc_t acc[TILES];
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < CH / 4; ++ks) {
         const int xi = ks * 4 + kq;
-        cplx<T> a0, c0, a1, c1, bv;
-        if constexpr (L::split) {
-          a0 = {ldsr[sa0 + xi], ldsr[sa0 + CH + xi]};
-          c0 = {ldsr[sc0 + xi], ldsr[sc0 + CH + xi]};
-          a1 = {ldsr[sa1 + xi], ldsr[sa1 + CH + xi]};
-          c1 = {ldsr[sc1 + xi], ldsr[sc1 + CH + xi]};
+        cplx<T> bv;
+        if constexpr (L::split)
           bv = {ldsr[sb + xi], ldsr[sb + CH + xi]};
-        } else {
-          a0 = lds[sa0 + xi];
-          c0 = lds[sc0 + xi];
-          a1 = lds[sa1 + xi];
-          c1 = lds[sc1 + xi];
+        else
           bv = lds[sb + xi];
+        T pr[TILES], pn[TILES];
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) {
+          cplx<T> a, c;
+          if constexpr (L::split) {
+            a = {ldsr[sa[t] + xi], ldsr[sa[t] + CH + xi]};
+            c = {ldsr[sc[t] + xi], ldsr[sc[t] + CH + xi]};
+          } else {
+            a = lds[sa[t] + xi];
+            c = lds[sc[t] + xi];
+          }
+          // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
+          pr[t] = a.x * c.x + a.y * c.y;
+          pn[t] = a.x * c.y - a.y * c.x;
         }
-        // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
-        const T p0r = a0.x * c0.x + a0.y * c0.y, p0n = a0.x * c0.y - a0.y * c0.x;
-        const T p1r = a1.x * c1.x + a1.y * c1.y, p1n = a1.x * c1.y - a1.y * c1.x;
-        r0 = Mfma<T>::step(p0r, bv.x, r0);
-        r1 = Mfma<T>::step(p1r, bv.x, r1);
-        i0 = Mfma<T>::step(p0n, bv.y, i0);
-        i1 = Mfma<T>::step(p1n, bv.y, i1);
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], bv.x, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bv.y, acc[t]);
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        out0[k] += double(r0[k]) + double(i0[k]);
-        out1[k] += double(r1[k]) + double(i1[k]);
-      }
+      for (int t = 0; t < TILES; ++t)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][k]);
     }
   }
   if (active) {
-    double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kItemOut;
+    double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kOut;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = Mfma<T>::out_row(kq, k);
-      o[r * kTileN + row] = out0[k];
-      o[(16 + r) * kTileN + row] = out1[k];
-    }
+    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[(16 * t + Mfma<T>::out_row(kq, k)) * kTileN + row] = out[t][k];
   }
 }
 

@@ -58,10 +58,13 @@ int count_lm(int l_max, int m_max) {
   return n;
 }
 
-std::string build_tables(const Binning& b, int n_threads, Tables* out) {
+std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out) {
   Tables& T = *out;
   T = Tables();
   T.bin = b;
+  T.k3 = k3;
+  const int ppi = k3.pairs_per_item;
+  if (ppi != 32 && ppi != 64) return "pairs per work item must be 32 or 64";
   const int ng = b.ng;
   T.ng = ng;
   if (n_threads < 1) n_threads = 1;
@@ -338,7 +341,7 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
   // ---- K3 work items.  Pairs are (slot A ring, slot C ring); the N dimension
   // is the slot-B ring.  For every pair the kept slot-B rings are cut into
   // windows of kTileN consecutive rings; windows are packed greedily into
-  // items of up to kPairsPerItem pairs sharing one window.
+  // items of up to ppi pairs sharing one window.
   std::vector<int64_t> combo_item_slot;  // per combination in (pt, enumeration) order
   combo_item_slot.reserve(total);
   std::vector<std::vector<int64_t>> pt_combo_slot(pts.size());
@@ -378,7 +381,7 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
     };
     std::vector<Item> its;
     for (int s = 0; s < int(segs.size()); ++s) {
-      if (its.empty() || int(its.back().segs.size()) == kPairsPerItem || segs[s].hi >= its.back().lo + kTileN)
+      if (its.empty() || int(its.back().segs.size()) == ppi || segs[s].hi >= its.back().lo + kTileN)
         its.push_back({segs[s].lo, {}});
       its.back().segs.push_back(s);
     }
@@ -423,7 +426,7 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
       for (size_t ii = g0; ii < g1; ++ii) {
         ItemDesc& d = descs[ii - g0];
         const Item& it = its[ii];
-        for (int p = 0; p < kPairsPerItem; ++p) {
+        for (int p = 0; p < ppi; ++p) {
           if (p < int(it.segs.size())) {
             const Seg& sg = segs[it.segs[p]];
             d.a_slot[p] = slot(side(sg.ra, a));
@@ -442,7 +445,7 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
       for (size_t ii = g0; ii < g1; ++ii) {
         ItemDesc& d = descs[ii - g0];
         const Item& it = its[ii];
-        for (int p = int(it.segs.size()); p < kPairsPerItem; ++p) d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
+        for (int p = int(it.segs.size()); p < ppi; ++p) d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
         for (int j = 0; j < kTileN; ++j) {
           const int rbj = it.lo + j;
           const int32_t sidx = side(rbj, bb);
@@ -451,9 +454,9 @@ std::string build_tables(const Binning& b, int n_threads, Tables* out) {
         const int64_t item_index = int64_t(T.items.size()) + int64_t(ii - g0);
         for (int p = 0; p < int(it.segs.size()); ++p) {
           const Seg& sg = segs[it.segs[p]];
-          for (int ci : sg.idx) slot_of[ci] = item_index * (kPairsPerItem * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
+          for (int ci : sg.idx) slot_of[ci] = item_index * (ppi * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
         }
-        T.dense_terms += double(kPairsPerItem) * kTileN;
+        T.dense_terms += double(ppi) * kTileN;
       }
       T.max_group_sides = std::max(T.max_group_sides, zero_slot + 1);
       for (auto& d : descs) T.items.push_back(d);

@@ -10,6 +10,11 @@
 
 namespace bk {
 
+// Shape of the contraction's work items (chosen per plan).
+struct K3Shape {
+  int pairs_per_item = 32;  // 32 (two row tiles per wave) or 64 (four)
+};
+
 struct Binning {
   int ng = 0;
   double box_len = 0.0;  // L
@@ -20,9 +25,9 @@ struct Binning {
 };
 
 // Sizes of the K3 work decomposition.
-constexpr int kTileN = 16;        // third-slot rings per work item (MFMA N)
-constexpr int kPairsPerItem = 32;  // ring pairs per work item (two 16-row MFMA tiles)
-constexpr int kItemsPerGroup = 8;  // work items (waves) per workgroup, all on one plane triple
+constexpr int kTileN = 16;           // third-slot rings per work item (MFMA N)
+constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 2 or 4 tiles
+constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, all on one plane triple
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
 
 // One workgroup of the contraction kernel: a canonical plane triple and up to
@@ -36,16 +41,17 @@ struct GroupDesc {
   int32_t pad[3];
 };
 
-// One work item: kPairsPerItem pairs of (slot A ring, slot C ring) and kTileN
-// slot-B rings.  Indices are LDS slots of the owning group.
+// One work item: up to kMaxPairsPerItem pairs of (slot A ring, slot C ring)
+// and kTileN slot-B rings.  Indices are LDS slots of the owning group.
 struct ItemDesc {
-  uint8_t a_slot[kPairsPerItem];
-  uint8_t c_slot[kPairsPerItem];
+  uint8_t a_slot[kMaxPairsPerItem];
+  uint8_t c_slot[kMaxPairsPerItem];
   uint8_t b_slot[kTileN];
 };
 
 struct Tables {
   Binning bin;
+  K3Shape k3;
   int ng = 0, nr = 0, nmax = 0;
   std::vector<int64_t> edge3;              // 3 * R_r (R_r rational with denominator 3), r = 0..nr
   std::vector<double> mean_radius;         // K_r, r = 1..nr (index r-1)
@@ -66,7 +72,7 @@ struct Tables {
   int64_t n_self_partner = 0;             // combinations equal to their n -> -n partner
   int64_t n_canonical_planes = 0;
   std::vector<int32_t> combo_bin;        // per combination
-  std::vector<int64_t> combo_slot;       // index into the K3 output (item * 512 + pair * 16 + col)
+  std::vector<int64_t> combo_slot;       // index into the K3 output (item * pairs * 16 + pair * 16 + col)
   std::vector<double> combo_coef;        // [combo][n_lm]: final coefficient on Re S
   std::vector<int64_t> bin_ptr;          // combinations sorted by bin: CSR offsets [n_bins + 1]
   std::vector<int64_t> bin_count;        // sum of mult * N_tri per bin
@@ -83,7 +89,7 @@ struct Tables {
 };
 
 // Builds everything; returns "" on success or an error message.
-std::string build_tables(const Binning& b, int n_threads, Tables* out);
+std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out);
 
 // Number of (l, m) outputs for l_max, m_max (even l only).
 int count_lm(int l_max, int m_max);
