@@ -122,6 +122,19 @@ bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
  * forward FFT, ring FFTs, triple products, binning (hipEvents on the stream). */
 bk_status bk_get_stage_times(bk_plan plan, double* ms, size_t cap);
 
+/* A group of plans on one device (for example fields of different N_g, each
+ * plan batched) estimated together.  On the first bk_group_estimate the
+ * kernels of every plan are captured into one hipGraph with one branch per
+ * plan; every call replays it with a single hipGraphLaunch on hip_stream.
+ * The capture uses the batch each plan has loaded; loading a different batch
+ * size into a member plan makes the next call capture again.  Every member
+ * must have a grid loaded.  The plans stay owned by the caller and must
+ * outlive the group; results are read from each plan with bk_get_*. */
+typedef struct bk_group_s* bk_group;
+bk_status bk_group_create(const bk_plan* plans, int n_plans, bk_group* out);
+bk_status bk_group_estimate(bk_group group, void* hip_stream);
+bk_status bk_group_destroy(bk_group group);
+
 /* Host-only geometry (no device needed): the same per-bin sums of N_tri that
  * bk_get_triangle_counts returns, int64 [n_k1][n_mu][n_t], and optionally the
  * number of kept combinations (counting an n -> -n partner pair once).  Useful

@@ -74,6 +74,9 @@ _SIGS = {
     "bk_debug_get_buffer": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                             ctypes.POINTER(ctypes.c_size_t)],
     "bk_debug_mfma_probe": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+    "bk_group_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+    "bk_group_estimate": [ctypes.c_void_p, ctypes.c_void_p],
+    "bk_group_destroy": [ctypes.c_void_p],
     "bk_count_triangles": [ctypes.POINTER(bk_binning), ctypes.POINTER(ctypes.c_int64), ctypes.c_size_t,
                            ctypes.POINTER(ctypes.c_int64)],
 }
@@ -212,6 +215,21 @@ def bk_debug_mfma_probe(prec: int) -> np.ndarray:
     out = np.empty(256, dtype=np.float64)
     _check(lib().bk_debug_mfma_probe(int(prec), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 256))
     return out.reshape(64, 4)
+
+
+def bk_group_create(plans) -> int:
+    arr = (ctypes.c_void_p * len(plans))(*plans)
+    out = ctypes.c_void_p()
+    _check(lib().bk_group_create(arr, len(plans), ctypes.byref(out)))
+    return out.value
+
+
+def bk_group_estimate(group: int, stream: int = 0):
+    _check(lib().bk_group_estimate(ctypes.c_void_p(group), ctypes.c_void_p(stream)))
+
+
+def bk_group_destroy(group: int):
+    _check(lib().bk_group_destroy(ctypes.c_void_p(group)))
 
 
 class Estimator:

@@ -57,6 +57,7 @@ struct bk_plan_s {
   int batch = 0;          // fields currently loaded
   int in_dtype = 0;       // dtype of the loaded fields
   int estimated = 0;      // a completed estimate is enqueued for `batch`
+  int timed = 0;          // the stage events belong to the last estimate
   hipStream_t stream = nullptr;
   size_t elem = 8;        // sizeof(complex T) / 2
   bk::FftShape sh{};
@@ -140,7 +141,7 @@ int pick_tb(int n, size_t elem_bytes) {
 }
 
 template <typename T>
-bk_status launch_all(bk_plan p, hipStream_t st) {
+bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   using C = bk::cplx<T>;
   const int n = p->sh.n;
   const int B = p->batch;
@@ -152,7 +153,7 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
   C* G = reinterpret_cast<C*>(p->d_G);
   C* D = reinterpret_cast<C*>(p->d_D);
 
-  BK_HIP(hipEventRecord(p->ev[0], st));
+  if (timing) BK_HIP(hipEventRecord(p->ev[0], st));
   // K1: z pass (real input), y rows, x columns
   {
     dim3 grid(n * (n / tb), B);
@@ -170,7 +171,7 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
     hipLaunchKernelGGL((bk::k_cols_kernel<T>), dim3(n / tb, B * p->nkeep), dim3(256), lds_fft, st, F, tw, p->sh, tb);
     BK_HIP(hipGetLastError());
   }
-  BK_HIP(hipEventRecord(p->ev[1], st));
+  if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
   // K2: ring rows, then columns
   if (p->n_sides > 0) {
     dim3 g1((p->n_k2lines + tb - 1) / tb, B);
@@ -183,7 +184,7 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
                        int(p->n_sides), tw, p->sh, tb);
     BK_HIP(hipGetLastError());
   }
-  BK_HIP(hipEventRecord(p->ev[2], st));
+  if (timing) BK_HIP(hipEventRecord(p->ev[2], st));
   // K3: triple products
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
@@ -196,14 +197,18 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
       BK_K3(64, 2);
     else if (p->k3_chunk == 64)
       BK_K3(64, 4);
-    else if (tiles == 2)
+    else if (p->k3_chunk == 32 && tiles == 2)
       BK_K3(32, 2);
-    else
+    else if (p->k3_chunk == 32)
       BK_K3(32, 4);
+    else if (tiles == 2)
+      BK_K3(16, 2);
+    else
+      BK_K3(16, 4);
 #undef BK_K3
     BK_HIP(hipGetLastError());
   }
-  BK_HIP(hipEventRecord(p->ev[3], st));
+  if (timing) BK_HIP(hipEventRecord(p->ev[3], st));
   // K4: binning
   {
     const int n_bins = p->tab.bin.n_k1 * p->tab.bin.n_mu * p->tab.bin.n_t;
@@ -212,7 +217,7 @@ bk_status launch_all(bk_plan p, hipStream_t st) {
                        p->d_combo_slot, p->d_coef, p->d_empty, int(p->tab.lm_l.size()), n_bins, p->norm, p->d_B);
     BK_HIP(hipGetLastError());
   }
-  BK_HIP(hipEventRecord(p->ev[4], st));
+  if (timing) BK_HIP(hipEventRecord(p->ev[4], st));
   return BK_OK;
 }
 
@@ -396,7 +401,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   {
     // largest chunk whose staging fits 64 KiB of LDS and the per-thread load budget
     p->k3_chunk = 0;
-    for (int ch : {64, 32}) {
+    for (int ch : {64, 32, 16}) {
       if (X_ % ch != 0) continue;
       const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
       const size_t lds = size_t(T.max_group_sides) * slot;
@@ -463,10 +468,11 @@ bk_status bk_estimate(bk_plan p, void* hip_stream) {
   if (p->batch < 1) return fail(BK_ERR_STATE, "no grid loaded");
   BK_HIP(hipSetDevice(p->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  bk_status s = p->prec == BK_F32 ? launch_all<float>(p, st) : launch_all<double>(p, st);
+  bk_status s = p->prec == BK_F32 ? launch_all<float>(p, st, true) : launch_all<double>(p, st, true);
   if (s != BK_OK) return s;
   p->stream = st;
   p->estimated = 1;
+  p->timed = 1;
   return BK_OK;
 }
 
@@ -549,7 +555,7 @@ bk_status bk_get_stage_times(bk_plan p, double* ms, size_t cap) {
   g_last_error.clear();
   if (!p || !ms) return fail(BK_ERR_ARG, "null argument");
   if (cap < 4) return fail(BK_ERR_SIZE, "need 4 entries");
-  if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run");
+  if (!p->estimated || !p->timed) return fail(BK_ERR_STATE, "no individually launched estimate has been run");
   BK_HIP(hipSetDevice(p->device));
   BK_HIP(hipEventSynchronize(p->ev[4]));
   for (int i = 0; i < 4; ++i) {
@@ -625,6 +631,143 @@ bk_status bk_debug_mfma_probe(int prec, double* out, size_t cap) {
   if (e == hipSuccess) e = hipMemcpy(out, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   if (e != hipSuccess) return fail(BK_ERR_HIP, std::string("mfma probe: ") + hipGetErrorString(e));
+  return BK_OK;
+}
+
+
+}  // extern "C"
+
+struct bk_group_s {
+  std::vector<bk_plan> plans;
+  std::vector<int> captured_batch;
+  int device = 0;
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void group_release(bk_group g) {
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (auto e : g->join)
+    if (e) (void)hipEventDestroy(e);
+  if (g->fork) (void)hipEventDestroy(g->fork);
+  for (auto s : g->side)
+    if (s) (void)hipStreamDestroy(s);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+}
+
+bk_status group_capture(bk_group g) {
+  if (g->exec) {
+    BK_HIP(hipGraphExecDestroy(g->exec));
+    g->exec = nullptr;
+  }
+  if (g->graph) {
+    BK_HIP(hipGraphDestroy(g->graph));
+    g->graph = nullptr;
+  }
+  BK_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+  bk_status st = BK_OK;
+  hipError_t he = hipEventRecord(g->fork, g->cap);
+  for (size_t i = 0; i < g->plans.size() && st == BK_OK && he == hipSuccess; ++i) {
+    bk_plan p = g->plans[i];
+    he = hipStreamWaitEvent(g->side[i], g->fork, 0);
+    if (he != hipSuccess) break;
+    st = p->prec == BK_F32 ? launch_all<float>(p, g->side[i], false) : launch_all<double>(p, g->side[i], false);
+    if (st != BK_OK) break;
+    he = hipEventRecord(g->join[i], g->side[i]);
+    if (he == hipSuccess) he = hipStreamWaitEvent(g->cap, g->join[i], 0);
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t he_end = hipStreamEndCapture(g->cap, &graph);
+  if (st != BK_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (he != hipSuccess || he_end != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(BK_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(he != hipSuccess ? he : he_end));
+  }
+  g->graph = graph;
+  BK_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  for (size_t i = 0; i < g->plans.size(); ++i) g->captured_batch[i] = g->plans[i]->batch;
+  return BK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bk_status bk_group_create(const bk_plan* plans, int n, bk_group* out) {
+  g_last_error.clear();
+  if (!plans || !out || n < 1) return fail(BK_ERR_ARG, "need at least one plan");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(BK_ERR_ARG, "null plan in group");
+    if (plans[i]->device != plans[0]->device) return fail(BK_ERR_ARG, "all plans of a group must use one device");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return fail(BK_ERR_ARG, "a plan appears twice in the group");
+  }
+  BK_HIP(hipSetDevice(plans[0]->device));
+  bk_group g = new (std::nothrow) bk_group_s();
+  if (!g) return fail(BK_ERR_OOM, "host allocation failed");
+  g->plans.assign(plans, plans + n);
+  g->captured_batch.assign(n, -1);
+  g->device = plans[0]->device;
+  g->side.assign(n, nullptr);
+  g->join.assign(n, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    group_release(g);
+    delete g;
+    return fail(BK_ERR_HIP, std::string("group streams: ") + hipGetErrorString(e));
+  }
+  *out = g;
+  return BK_OK;
+}
+
+bk_status bk_group_estimate(bk_group g, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(BK_ERR_ARG, "null group");
+  BK_HIP(hipSetDevice(g->device));
+  bool recapture = g->exec == nullptr;
+  for (size_t i = 0; i < g->plans.size(); ++i) {
+    if (g->plans[i]->batch < 1) return fail(BK_ERR_STATE, "a plan of the group has no grid loaded");
+    if (g->plans[i]->batch != g->captured_batch[i]) recapture = true;
+  }
+  if (recapture) {
+    // the members' inputs were loaded on other streams: finish those copies first
+    for (auto p : g->plans) BK_HIP(hipStreamSynchronize(p->stream));
+    bk_status st = group_capture(g);
+    if (st != BK_OK) return st;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  BK_HIP(hipGraphLaunch(g->exec, st));
+  for (auto p : g->plans) {
+    p->stream = st;
+    p->estimated = 1;
+    p->timed = 0;
+  }
+  return BK_OK;
+}
+
+bk_status bk_group_destroy(bk_group g) {
+  g_last_error.clear();
+  if (!g) return fail(BK_ERR_ARG, "null group");
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  group_release(g);
+  delete g;
   return BK_OK;
 }
 

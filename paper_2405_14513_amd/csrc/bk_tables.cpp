@@ -10,7 +10,6 @@
 #include <atomic>
 #include <cmath>
 #include <map>
-#include <numeric>
 #include <thread>
 
 namespace bk {
@@ -329,6 +328,10 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     }
   }
   T.n_combos = total;
+  for (size_t ip = 0; ip < pts.size(); ++ip) {
+    std::vector<double>().swap(per_pt_d[ip]);
+    std::vector<double>().swap(per_pt_kmt[ip]);
+  }
   T.bin_mean.assign(size_t(n_bins) * 3, std::nan(""));
   for (int i = 0; i < n_bins; ++i)
     if (mean_w[i] > 0)
@@ -469,44 +472,30 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   T.dense_terms *= X;
   T.useful_terms *= X;
 
-  // ---- per-combination coefficients, sorted by bin (stable, in pt order)
-  std::vector<std::pair<int32_t, int64_t>> order;  // (bin, running index)
-  order.reserve(total);
-  std::vector<int64_t> flat_slot;
-  std::vector<double> flat_coef;
-  flat_slot.reserve(total);
-  flat_coef.reserve(size_t(total) * nlm);
-  std::vector<int32_t> flat_bin;
-  flat_bin.reserve(total);
-  const double vol = b.box_len * b.box_len * b.box_len;
-  for (size_t ip = 0; ip < pts.size(); ++ip) {
-    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
-      const ComboRec& cr = per_pt[ip][i];
-      flat_bin.push_back(cr.bin);
-      flat_slot.push_back(pt_combo_slot[ip][i]);
-      for (int j = 0; j < nlm; ++j) {
-        const double den = T.bin_den[size_t(j) * n_bins + cr.bin];
-        const double coef = den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den : 0.0;
-        flat_coef.push_back(coef);
-      }
-    }
-  }
-  (void)vol;
-  std::vector<int64_t> perm(total);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return flat_bin[x] < flat_bin[y]; });
+  // ---- per-combination coefficients in bin order (counting sort, stable in pt order)
+  T.bin_ptr.assign(n_bins + 1, 0);
+  for (size_t ip = 0; ip < pts.size(); ++ip)
+    for (const ComboRec& cr : per_pt[ip]) T.bin_ptr[cr.bin + 1] += 1;
+  for (int i = 0; i < n_bins; ++i) T.bin_ptr[i + 1] += T.bin_ptr[i];
+  std::vector<int64_t> fill(T.bin_ptr.begin(), T.bin_ptr.end() - 1);
   T.combo_bin.resize(total);
   T.combo_slot.resize(total);
   T.combo_coef.resize(size_t(total) * nlm);
-  T.bin_ptr.assign(n_bins + 1, 0);
-  for (int64_t i = 0; i < total; ++i) {
-    const int64_t src = perm[i];
-    T.combo_bin[i] = flat_bin[src];
-    T.combo_slot[i] = flat_slot[src];
-    for (int j = 0; j < nlm; ++j) T.combo_coef[size_t(i) * nlm + j] = flat_coef[size_t(src) * nlm + j];
-    T.bin_ptr[flat_bin[src] + 1] += 1;
+  for (size_t ip = 0; ip < pts.size(); ++ip) {
+    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
+      const ComboRec& cr = per_pt[ip][i];
+      const int64_t pos = fill[cr.bin]++;
+      T.combo_bin[pos] = cr.bin;
+      T.combo_slot[pos] = pt_combo_slot[ip][i];
+      for (int j = 0; j < nlm; ++j) {
+        const double den = T.bin_den[size_t(j) * n_bins + cr.bin];
+        T.combo_coef[size_t(pos) * nlm + j] = den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den : 0.0;
+      }
+    }
+    std::vector<ComboRec>().swap(per_pt[ip]);
+    std::vector<double>().swap(per_pt_w[ip]);
+    std::vector<int64_t>().swap(pt_combo_slot[ip]);
   }
-  for (int i = 0; i < n_bins; ++i) T.bin_ptr[i + 1] += T.bin_ptr[i];
   return "";
 }
 
