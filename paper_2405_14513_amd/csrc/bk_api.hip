@@ -91,7 +91,11 @@ struct bk_plan_s {
   bk::K2Line* d_k2lines = nullptr;
   long n_k2lines = 0;
   long* d_bin_ptr = nullptr;
-  long* d_combo_slot = nullptr;
+  long* d_chunk_begin = nullptr;  // combination index where each K4 chunk starts [n_chunks + 1]
+  long* d_bin_chunk = nullptr;    // first chunk of each bin [n_bins + 1]
+  double* d_part = nullptr;       // K4 partial sums [max_batch][n_chunks][n_lm]
+  long n_chunks = 0;
+  int32_t* d_combo_slot = nullptr;
   double* d_coef = nullptr;
   unsigned char* d_empty = nullptr;
   hipEvent_t ev[5] = {};
@@ -126,17 +130,21 @@ void release(bk_plan p) {
   void* ptrs[] = {p->d_in,         p->d_F,          p->d_G,          p->d_D,          p->d_S,
                   p->d_B,          p->d_tw,         p->d_groups,     p->d_items,      p->d_group_sides,
                   p->d_mode_ring,  p->d_side_ring,  p->d_side_plane, p->d_side_u,     p->d_goff,
-                  p->d_k2lines,    p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty};
+                  p->d_k2lines,    p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty,
+                  p->d_chunk_begin, p->d_bin_chunk, p->d_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->have_events)
     for (auto& e : p->ev) (void)hipEventDestroy(e);
 }
 
+// LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
+size_t fft_lds_bytes(int n, int tb, size_t elem_bytes) { return (size_t(n) + size_t(2) * tb * (n + 1)) * elem_bytes; }
+
 int pick_tb(int n, size_t elem_bytes) {
-  // two LDS buffers of tb lines, at most 64 KiB, tb divides n
+  // lines per block: at most 16, dividing n, LDS at most 72 KiB (two blocks per CU)
   int tb = 16;
-  while (tb > 1 && (size_t(2) * tb * n * elem_bytes > 65536 || n % tb != 0)) tb /= 2;
+  while (tb > 1 && (fft_lds_bytes(n, tb, elem_bytes) > 73728 || n % tb != 0)) tb /= 2;
   return tb;
 }
 
@@ -147,7 +155,7 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   const int B = p->batch;
   const size_t cs = sizeof(C);
   const int tb = pick_tb(n, cs);
-  const size_t lds_fft = size_t(2) * tb * n * cs;
+  const size_t lds_fft = fft_lds_bytes(n, tb, cs);
   const C* tw = reinterpret_cast<const C*>(p->d_tw);
   C* F = reinterpret_cast<C*>(p->d_F);
   C* G = reinterpret_cast<C*>(p->d_G);
@@ -213,8 +221,23 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   {
     const int n_bins = p->tab.bin.n_k1 * p->tab.bin.n_mu * p->tab.bin.n_t;
     dim3 g4(n_bins, B);
-    hipLaunchKernelGGL(bk::k4_bin_kernel, g4, dim3(64), 0, st, p->d_S, p->n_items * long(p->item_out), p->d_bin_ptr,
-                       p->d_combo_slot, p->d_coef, p->d_empty, int(p->tab.lm_l.size()), n_bins, p->norm, p->d_B);
+    const int nlm = int(p->tab.lm_l.size());
+    const long s_per = p->n_items * long(p->item_out);
+    if (p->n_chunks > 0) {
+      dim3 gp(p->n_chunks, B);
+      if (nlm <= 16)
+        hipLaunchKernelGGL(bk::k4_partial_kernel<16>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+      else if (nlm <= 32)
+        hipLaunchKernelGGL(bk::k4_partial_kernel<32>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+      else
+        hipLaunchKernelGGL(bk::k4_partial_kernel<64>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+      BK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, p->d_part, p->n_chunks, p->d_bin_chunk, p->d_empty,
+                       nlm, n_bins, p->norm, p->d_B);
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[4], st));
@@ -388,7 +411,26 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(put(p, &p->d_goff, goff.data(), goff.size()));
   TRY(put(p, &p->d_k2lines, lines.data(), lines.size()));
   std::vector<long> bin_ptr(T.bin_ptr.begin(), T.bin_ptr.end());
-  std::vector<long> cslot(T.combo_slot.begin(), T.combo_slot.end());
+  if (long(p->n_items) * p->item_out * max_batch >= (1L << 31)) {
+    release(p);
+    delete p;
+    return fail(BK_ERR_ARG, "too many work items for 32-bit output slots");
+  }
+  std::vector<int32_t> cslot(T.combo_slot.begin(), T.combo_slot.end());
+  {
+    std::vector<long> chunk_begin, bin_chunk(n_bins + 1, 0);
+    for (int bin = 0; bin < n_bins; ++bin) {
+      bin_chunk[bin] = long(chunk_begin.size());
+      for (long c = bin_ptr[bin]; c < bin_ptr[bin + 1]; c += bk::kK4Chunk) chunk_begin.push_back(c);
+    }
+    bin_chunk[n_bins] = long(chunk_begin.size());
+    p->n_chunks = long(chunk_begin.size());
+    chunk_begin.push_back(bin_ptr[n_bins]);
+    // chunks are consecutive and start at every bin start, so none crosses a bin
+    TRY(put(p, &p->d_chunk_begin, chunk_begin.data(), chunk_begin.size()));
+    TRY(put(p, &p->d_bin_chunk, bin_chunk.data(), bin_chunk.size()));
+    TRY(dalloc(p, reinterpret_cast<void**>(&p->d_part), size_t(max_batch) * std::max(1L, p->n_chunks) * nlm * 8));
+  }
   TRY(put(p, &p->d_bin_ptr, bin_ptr.data(), bin_ptr.size()));
   TRY(put(p, &p->d_combo_slot, cslot.data(), cslot.size()));
   TRY(put(p, &p->d_coef, T.combo_coef.data(), T.combo_coef.size()));

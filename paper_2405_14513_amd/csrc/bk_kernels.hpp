@@ -28,21 +28,27 @@ __global__ __launch_bounds__(256) void k1_z_kernel(const Tin* __restrict__ delta
                                                    T scale) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b1 = b0 + tb * n;
+  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b1 = b0 + tb * ls;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
   const int ytiles = n / tb;
   const int x = blockIdx.x / ytiles;
   const int y0 = (blockIdx.x % ytiles) * tb;
   const int b = blockIdx.y;
   const size_t n3 = size_t(n) * n * n;
   const Tin* src = delta + size_t(b) * n3 + (size_t(x) * n + y0) * n;
-  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) b0[q] = {T(src[q]) * scale, T(0)};
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+    const int l = q / n, i = q - l * n;
+    b0[l * ls + i] = {T(src[q]) * scale, T(0)};
+  }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   cplx<T>* dst = F + size_t(b) * nkeep * n * n + size_t(x) * n + y0;
   for (int q = threadIdx.x; q < tb * nkeep; q += blockDim.x) {
     const int kz = q / tb, l = q - kz * tb;
-    dst[size_t(kz) * n * n + l] = res[l * n + kz];
+    dst[size_t(kz) * n * n + l] = res[l * ls + kz];
   }
 }
 
@@ -52,15 +58,24 @@ __global__ __launch_bounds__(256) void k_rows_kernel(cplx<T>* __restrict__ data,
                                                      FftShape sh, int tb, long lines_total) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b1 = b0 + tb * n;
+  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b1 = b0 + tb * ls;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
   const long line0 = long(blockIdx.x) * tb;
   const int lines = int(min(long(tb), lines_total - line0));
   cplx<T>* base = data + line0 * n;
-  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) b0[q] = base[q];
+  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) {
+    const int l = q / n, i = q - l * n;
+    b0[l * ls + i] = base[q];
+  }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw, sh, lines, n);
-  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) base[q] = res[q];
+  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, lines, ls);
+  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) {
+    const int l = q / n, i = q - l * n;
+    base[q] = res[l * ls + i];
+  }
 }
 
 // In-place transform of strided lines: for each plane p (grid.y), the lines are
@@ -70,19 +85,22 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
                                                      FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b1 = b0 + tb * n;
+  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b1 = b0 + tb * ls;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
   const int c0 = blockIdx.x * tb;
   cplx<T>* base = data + size_t(blockIdx.y) * n * n + c0;
   for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
     const int i = q / tb, l = q - i * tb;
-    b0[l * n + i] = base[size_t(i) * n + l];
+    b0[l * ls + i] = base[size_t(i) * n + l];
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
     const int i = q / tb, l = q - i * tb;
-    base[size_t(i) * n + l] = res[l * n + i];
+    base[size_t(i) * n + l] = res[l * ls + i];
   }
 }
 
@@ -105,8 +123,11 @@ __global__ __launch_bounds__(256) void k2_rows_kernel(const cplx<T>* __restrict_
                                                       const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b1 = b0 + tb * n;
+  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b1 = b0 + tb * ls;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
   const long l0 = long(blockIdx.x) * tb;
   const int cnt = int(min(long(tb), n_lines - l0));
   const int b = blockIdx.y;
@@ -121,15 +142,15 @@ __global__ __launch_bounds__(256) void k2_rows_kernel(const cplx<T>* __restrict_
       const int uxi = ln.ux < 0 ? ln.ux + n : ln.ux;
       v = Fb[(size_t(side_plane[ln.side]) * n + uxi) * n + uyi];
     }
-    b0[l * n + uyi] = v;
+    b0[l * ls + uyi] = v;
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw, sh, cnt, n);
+  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, cnt, ls);
   cplx<T>* Gb = G + size_t(b) * g_total;
   for (int q = threadIdx.x; q < cnt * n; q += blockDim.x) {
     const int l = q / n, y = q - l * n;
     const K2Line ln = lines[l0 + l];
-    Gb[goff[ln.side] + size_t(ln.ux + side_u[ln.side]) * n + y] = res[l * n + y];
+    Gb[goff[ln.side] + size_t(ln.ux + side_u[ln.side]) * n + y] = res[l * ls + y];
   }
 }
 
@@ -142,8 +163,11 @@ __global__ __launch_bounds__(256) void k2_cols_kernel(const cplx<T>* __restrict_
                                                       const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  cplx<T>* b0 = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b1 = b0 + tb * n;
+  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b1 = b0 + tb * ls;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
   const int ytiles = n / tb;
   const int s = blockIdx.x / ytiles;
   const int y0 = (blockIdx.x % ytiles) * tb;
@@ -155,14 +179,14 @@ __global__ __launch_bounds__(256) void k2_cols_kernel(const cplx<T>* __restrict_
     const int ux = i <= n / 2 ? i : i - n;
     cplx<T> v = {T(0), T(0)};
     if (ux >= -U && ux <= U) v = Gs[size_t(ux + U) * n + y0 + l];
-    b0[l * n + i] = v;
+    b0[l * ls + i] = v;
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw, sh, tb, n);
+  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   cplx<T>* Ds = D + (size_t(b) * n_sides + s) * size_t(n) * n;
   for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
     const int x = q / tb, l = q - x * tb;
-    Ds[size_t(x) * n + y0 + l] = res[l * n + x];
+    Ds[size_t(x) * n + y0 + l] = res[l * ls + x];
   }
 }
 
@@ -323,36 +347,47 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
       }
     }
     if (active) {
+      // Software pipeline over the CH/4 k-steps: the LDS operands of step
+      // ks+1 are read before the MFMAs of step ks are issued, and the pair
+      // products of a step are formed into their own registers.
       acc_t acc[TILES];
 #pragma unroll
       for (int t = 0; t < TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
+      cplx<T> a_n[TILES], c_n[TILES], b_n;
+      auto load_step = [&](int ks, cplx<T>* a, cplx<T>* c, cplx<T>& bvv) {
+        const int xi = ks * 4 + kq;
+        if constexpr (L::split) {
+          bvv = {ldsr[sb + xi], ldsr[sb + CH + xi]};
+#pragma unroll
+          for (int t = 0; t < TILES; ++t) {
+            a[t] = {ldsr[sa[t] + xi], ldsr[sa[t] + CH + xi]};
+            c[t] = {ldsr[sc[t] + xi], ldsr[sc[t] + CH + xi]};
+          }
+        } else {
+          bvv = lds[sb + xi];
+#pragma unroll
+          for (int t = 0; t < TILES; ++t) {
+            a[t] = lds[sa[t] + xi];
+            c[t] = lds[sc[t] + xi];
+          }
+        }
+      };
+      load_step(0, a_n, c_n, b_n);
 #pragma unroll
       for (int ks = 0; ks < CH / 4; ++ks) {
-        const int xi = ks * 4 + kq;
-        cplx<T> bv;
-        if constexpr (L::split)
-          bv = {ldsr[sb + xi], ldsr[sb + CH + xi]};
-        else
-          bv = lds[sb + xi];
+        // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
         T pr[TILES], pn[TILES];
 #pragma unroll
         for (int t = 0; t < TILES; ++t) {
-          cplx<T> a, c;
-          if constexpr (L::split) {
-            a = {ldsr[sa[t] + xi], ldsr[sa[t] + CH + xi]};
-            c = {ldsr[sc[t] + xi], ldsr[sc[t] + CH + xi]};
-          } else {
-            a = lds[sa[t] + xi];
-            c = lds[sc[t] + xi];
-          }
-          // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
-          pr[t] = a.x * c.x + a.y * c.y;
-          pn[t] = a.x * c.y - a.y * c.x;
+          pr[t] = a_n[t].x * c_n[t].x + a_n[t].y * c_n[t].y;
+          pn[t] = a_n[t].x * c_n[t].y - a_n[t].y * c_n[t].x;
         }
+        const T br = b_n.x, bi = b_n.y;
+        if (ks + 1 < CH / 4) load_step(ks + 1, a_n, c_n, b_n);
 #pragma unroll
-        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], bv.x, acc[t]);
+        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], br, acc[t]);
 #pragma unroll
-        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bv.y, acc[t]);
+        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bi, acc[t]);
       }
 #pragma unroll
       for (int t = 0; t < TILES; ++t)
@@ -382,42 +417,48 @@ __global__ __launch_bounds__(64) void mfma_probe_kernel(double* out) {
 }
 
 // ---------------------------------------------------------------- K4
-// One wave per (bin, batch): B[b][j][bin] = norm * sum_c coef[c][j] * S[slot[c]].
-__global__ __launch_bounds__(64) void k4_bin_kernel(const double* __restrict__ S, long s_per_batch,
-                                                    const long* __restrict__ bin_ptr,
-                                                    const long* __restrict__ combo_slot,
-                                                    const double* __restrict__ coef,
-                                                    const unsigned char* __restrict__ empty, int n_lm, int n_bins,
-                                                    double norm, double* __restrict__ B) {
-  const int bin = blockIdx.x;
+// Second-level binning in two passes.  The combinations of a bin are
+// contiguous (sorted by output slot) and cut into chunks of at most
+// kK4Chunk.  Pass 1: one wave per (chunk, field); lane l handles multipole
+// j = l % G of combination first + l / G (G = 16, 32 or 64 >= n_lm), so one
+// load reads 64 consecutive coefficients; lanes of one j are summed in a
+// fixed butterfly order into part[field][chunk][j].  Pass 2: per (bin, field)
+// the chunk partials are added in chunk order and scaled; empty bins are NaN.
+constexpr int kK4Chunk = 1024;
+
+template <int G>
+__global__ __launch_bounds__(64) void k4_partial_kernel(const double* __restrict__ S, long s_per_batch,
+                                                        const long* __restrict__ chunk_begin,
+                                                        const int32_t* __restrict__ combo_slot,
+                                                        const double* __restrict__ coef, int n_lm, long n_chunks,
+                                                        double* __restrict__ part) {
+  constexpr int per_iter = 64 / G;
+  const long ch = blockIdx.x;
   const int b = blockIdx.y;
   const int lane = threadIdx.x;
-  const long c0 = bin_ptr[bin], c1 = bin_ptr[bin + 1];
+  const int j = lane % G, cc = lane / G;
+  const long c0 = chunk_begin[ch], c1 = chunk_begin[ch + 1];
   const double* Sb = S + size_t(b) * s_per_batch;
-  for (int j0 = 0; j0 < n_lm; j0 += 16) {
-    double acc[16];
+  double acc = 0.0;
+  if (j < n_lm) {
+#pragma unroll 4
+    for (long c = c0 + cc; c < c1; c += per_iter) acc += coef[size_t(c) * n_lm + j] * Sb[combo_slot[c]];
+  }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-    for (long c = c0 + lane; c < c1; c += 64) {
-      const double s = Sb[combo_slot[c]];
-      const double* cf = coef + size_t(c) * n_lm + j0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j0 + j < n_lm) acc[j] += cf[j] * s;
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      double v = acc[j];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-      acc[j] = v;
-    }
-    if (lane == 0) {
-      for (int j = 0; j < 16 && j0 + j < n_lm; ++j) {
-        const int jj = j0 + j;
-        B[(size_t(b) * n_lm + jj) * n_bins + bin] =
-            empty[size_t(jj) * n_bins + bin] ? __builtin_nan("") : norm * acc[j];
-      }
-    }
+  for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane < n_lm) part[(size_t(b) * n_chunks + ch) * n_lm + lane] = acc;
+}
+
+__global__ __launch_bounds__(64) void k4_finish_kernel(const double* __restrict__ part, long n_chunks,
+                                                       const long* __restrict__ bin_chunk,
+                                                       const unsigned char* __restrict__ empty, int n_lm, int n_bins,
+                                                       double norm, double* __restrict__ B) {
+  const int bin = blockIdx.x;
+  const int b = blockIdx.y;
+  for (int j = threadIdx.x; j < n_lm; j += blockDim.x) {
+    double acc = 0.0;
+    for (long ch = bin_chunk[bin]; ch < bin_chunk[bin + 1]; ++ch) acc += part[(size_t(b) * n_chunks + ch) * n_lm + j];
+    B[(size_t(b) * n_lm + j) * n_bins + bin] = empty[size_t(j) * n_bins + bin] ? __builtin_nan("") : norm * acc;
   }
 }
 

@@ -496,6 +496,26 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     std::vector<double>().swap(per_pt_w[ip]);
     std::vector<int64_t>().swap(pt_combo_slot[ip]);
   }
+  // within each bin, order the combinations by output slot (locality of the S gather)
+  {
+    std::vector<int64_t> idx;
+    std::vector<int64_t> tmp_slot;
+    std::vector<double> tmp_coef;
+    for (int bin = 0; bin < n_bins; ++bin) {
+      const int64_t c0 = T.bin_ptr[bin], c1 = T.bin_ptr[bin + 1];
+      if (c1 - c0 < 2) continue;
+      idx.resize(c1 - c0);
+      for (int64_t i = 0; i < c1 - c0; ++i) idx[i] = c0 + i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return T.combo_slot[x] < T.combo_slot[y]; });
+      tmp_slot.resize(c1 - c0);
+      for (int64_t i = 0; i < c1 - c0; ++i) tmp_slot[i] = T.combo_slot[idx[i]];
+      std::copy(tmp_slot.begin(), tmp_slot.end(), T.combo_slot.begin() + c0);
+      tmp_coef.resize(size_t(c1 - c0) * nlm);
+      for (int64_t i = 0; i < c1 - c0; ++i)
+        for (int j = 0; j < nlm; ++j) tmp_coef[size_t(i) * nlm + j] = T.combo_coef[size_t(idx[i]) * nlm + j];
+      std::copy(tmp_coef.begin(), tmp_coef.end(), T.combo_coef.begin() + size_t(c0) * nlm);
+    }
+  }
   return "";
 }
 
