@@ -62,7 +62,6 @@ struct bk_plan_s {
   size_t elem = 8;        // sizeof(complex T) / 2
   bk::FftShape sh{};
   int nkeep = 0;
-  long g_total = 0;       // complex elements of G per field
   long n_sides = 0;
   long X = 0;
   long n_items = 0;
@@ -75,7 +74,6 @@ struct bk_plan_s {
 
   void* d_in = nullptr;       // [max_batch][N^3] of the input dtype
   void* d_F = nullptr;        // [max_batch][nkeep][N][N] complex
-  void* d_G = nullptr;        // [max_batch][g_total] complex
   void* d_D = nullptr;        // [max_batch][n_sides][N^2] complex
   double* d_S = nullptr;      // [max_batch][n_items][512]
   double* d_B = nullptr;      // [max_batch][n_lm][n_bins]
@@ -83,14 +81,13 @@ struct bk_plan_s {
   bk::GroupDesc* d_groups = nullptr;
   bk::ItemDesc* d_items = nullptr;
   int32_t* d_group_sides = nullptr;
-  int32_t* d_mode_ring = nullptr;
   int32_t* d_side_ring = nullptr;
   int32_t* d_side_plane = nullptr;
   int32_t* d_side_u = nullptr;
-  long* d_goff = nullptr;
-  bk::K2Line* d_k2lines = nullptr;
-  long n_k2lines = 0;
   long* d_bin_ptr = nullptr;
+  int32_t* d_ring_seg_off = nullptr;  // per ring: offset of its row table in d_ring_seg
+  int32_t* d_ring_seg = nullptr;      // per ring: start of each row u_x = -U..U in the mode list, plus end
+  int16_t* d_ring_mode_uy = nullptr;  // every ring's modes sorted by (u_x, u_y): u_y
   long* d_chunk_begin = nullptr;  // combination index where each K4 chunk starts [n_chunks + 1]
   long* d_bin_chunk = nullptr;    // first chunk of each bin [n_bins + 1]
   double* d_part = nullptr;       // K4 partial sums [max_batch][n_chunks][n_lm]
@@ -127,15 +124,21 @@ bk_status put(bk_plan p, V** dptr, const V* host, size_t count) {
 }
 
 void release(bk_plan p) {
-  void* ptrs[] = {p->d_in,         p->d_F,          p->d_G,          p->d_D,          p->d_S,
+  void* ptrs[] = {p->d_in,         p->d_F,          p->d_D,          p->d_S,
                   p->d_B,          p->d_tw,         p->d_groups,     p->d_items,      p->d_group_sides,
-                  p->d_mode_ring,  p->d_side_ring,  p->d_side_plane, p->d_side_u,     p->d_goff,
-                  p->d_k2lines,    p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty,
-                  p->d_chunk_begin, p->d_bin_chunk, p->d_part};
+                  p->d_side_ring,  p->d_side_plane, p->d_side_u,
+                  p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty,
+                  p->d_chunk_begin, p->d_bin_chunk, p->d_part,     p->d_ring_seg_off, p->d_ring_seg,
+                  p->d_ring_mode_uy};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->have_events)
     for (auto& e : p->ev) (void)hipEventDestroy(e);
+}
+
+template <typename T>
+constexpr bool prec_is_f32() {
+  return sizeof(T) == 4;
 }
 
 // LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
@@ -158,7 +161,6 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   const size_t lds_fft = fft_lds_bytes(n, tb, cs);
   const C* tw = reinterpret_cast<const C*>(p->d_tw);
   C* F = reinterpret_cast<C*>(p->d_F);
-  C* G = reinterpret_cast<C*>(p->d_G);
   C* D = reinterpret_cast<C*>(p->d_D);
 
   if (timing) BK_HIP(hipEventRecord(p->ev[0], st));
@@ -180,16 +182,15 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
-  // K2: ring rows, then columns
+  // K2: ring sums, pruned row DFT + column FFT per (side, column block)
   if (p->n_sides > 0) {
-    dim3 g1((p->n_k2lines + tb - 1) / tb, B);
-    hipLaunchKernelGGL((bk::k2_rows_kernel<T>), g1, dim3(256), lds_fft, st, F, G, p->d_k2lines, p->n_k2lines,
-                       p->d_side_ring, p->d_side_plane, p->d_side_u, p->d_goff, p->g_total, p->d_mode_ring,
-                       p->tab.lim, p->nkeep, tw, p->sh, tb);
-    BK_HIP(hipGetLastError());
-    dim3 g2(p->n_sides * (n / tb), B);
-    hipLaunchKernelGGL((bk::k2_cols_kernel<T>), g2, dim3(256), lds_fft, st, G, D, p->d_side_u, p->d_goff, p->g_total,
-                       int(p->n_sides), tw, p->sh, tb);
+    // columns per block: 8 (float32) or 4 (float64), i.e. 64-byte row segments and ~35 KiB of LDS
+    int tb2 = std::min(tb, prec_is_f32<T>() ? 8 : 4);
+    if (const char* v = std::getenv("BK_K2_TB")) tb2 = std::atoi(v);
+    dim3 g2(p->n_sides * (n / tb2), B);
+    hipLaunchKernelGGL((bk::k2_fused_kernel<T>), g2, dim3(256), fft_lds_bytes(n, tb2, cs), st, F, D, p->d_side_ring,
+                       p->d_side_plane, p->d_side_u, p->d_ring_seg_off, p->d_ring_seg, p->d_ring_mode_uy,
+                       int(p->n_sides), p->nkeep, tw, p->sh, tb2);
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[2], st));
@@ -356,21 +357,32 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   // B = sqrt(.) Re sum w S_Delta / (V N^2) / den;  S_Delta = (V/N^3)^3 S_DFT;  S_DFT = S' / scale^3
   p->norm = std::pow(vol / n3, 3) / (vol * double(n) * n) / std::pow(p->delta_scale, 3);
 
-  // K2 line list, row extents and G offsets
+  // row extent U of each side's ring: the largest |u_x| with |u_x| < R_r
   std::vector<int32_t> side_u(p->n_sides);
-  std::vector<long> goff(p->n_sides + 1, 0);
-  std::vector<bk::K2Line> lines;
   for (long s = 0; s < p->n_sides; ++s) {
-    const int r = T.side_ring[s];
-    const int64_t e3 = T.edge3[r];
+    const int64_t e3 = T.edge3[T.side_ring[s]];
     int U = 0;
-    while (9 * int64_t(U + 1) * (U + 1) < e3 * e3) ++U;  // largest |u_x| with |u_x| < R_r
+    while (9 * int64_t(U + 1) * (U + 1) < e3 * e3) ++U;
     side_u[s] = U;
-    goff[s + 1] = goff[s] + long(2 * U + 1) * n;
-    for (int ux = -U; ux <= U; ++ux) lines.push_back({int32_t(s), int32_t(ux)});
   }
-  p->g_total = goff[p->n_sides];
-  p->n_k2lines = long(lines.size());
+  // per ring: modes sorted by (u_x, u_y) and the start of each row u_x = -U_r..U_r
+  std::vector<int32_t> ring_seg_off(T.nr + 1, 0), ring_seg;
+  std::vector<int16_t> ring_mode_uy;
+  {
+    const int lim = T.lim, side_len = 2 * lim + 1;
+    for (int r = 1; r <= T.nr; ++r) {
+      int U = 0;
+      while (9 * int64_t(U + 1) * (U + 1) < T.edge3[r] * T.edge3[r]) ++U;
+      ring_seg_off[r - 1] = int32_t(ring_seg.size());
+      for (int ux = -U; ux <= U; ++ux) {
+        ring_seg.push_back(int32_t(ring_mode_uy.size()));
+        for (int uy = -lim; uy <= lim; ++uy)
+          if (T.mode_ring[size_t(ux + lim) * side_len + (uy + lim)] == r) ring_mode_uy.push_back(int16_t(uy));
+      }
+      ring_seg.push_back(int32_t(ring_mode_uy.size()));
+    }
+    ring_seg_off[T.nr] = int32_t(ring_seg.size());
+  }
 
   std::vector<double> twd(2 * size_t(n));
   for (int t = 0; t < n; ++t) {
@@ -393,7 +405,9 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   } while (0)
   TRY(dalloc(p, &p->d_in, size_t(max_batch) * size_t(n3) * 8));
   TRY(dalloc(p, &p->d_F, size_t(max_batch) * p->nkeep * size_t(n) * n * cs));
-  TRY(dalloc(p, &p->d_G, size_t(max_batch) * size_t(p->g_total) * cs));
+  TRY(put(p, &p->d_ring_seg_off, ring_seg_off.data(), ring_seg_off.size()));
+  TRY(put(p, &p->d_ring_seg, ring_seg.data(), ring_seg.size()));
+  TRY(put(p, &p->d_ring_mode_uy, ring_mode_uy.data(), ring_mode_uy.size()));
   TRY(dalloc(p, &p->d_D, size_t(max_batch) * size_t(p->n_sides) * size_t(p->X) * cs));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * p->item_out * 8));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_B), size_t(max_batch) * nlm * n_bins * 8));
@@ -404,12 +418,9 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(put(p, &p->d_groups, T.groups.data(), T.groups.size()));
   TRY(put(p, &p->d_items, T.items.data(), T.items.size()));
   TRY(put(p, &p->d_group_sides, T.group_sides.data(), T.group_sides.size()));
-  TRY(put(p, &p->d_mode_ring, T.mode_ring.data(), T.mode_ring.size()));
   TRY(put(p, &p->d_side_ring, T.side_ring.data(), T.side_ring.size()));
   TRY(put(p, &p->d_side_plane, T.side_plane.data(), T.side_plane.size()));
   TRY(put(p, &p->d_side_u, side_u.data(), side_u.size()));
-  TRY(put(p, &p->d_goff, goff.data(), goff.size()));
-  TRY(put(p, &p->d_k2lines, lines.data(), lines.size()));
   std::vector<long> bin_ptr(T.bin_ptr.begin(), T.bin_ptr.end());
   if (long(p->n_items) * p->item_out * max_batch >= (1L << 31)) {
     release(p);

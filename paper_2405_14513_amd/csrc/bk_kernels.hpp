@@ -3,8 +3,9 @@
 //  K1  forward 3-D DFT of the field, three batched 1-D passes (z, then y, then x),
 //      keeping only the k_parallel planes n = 0..nkeep-1 (Sec. II; negative
 //      planes follow from Delta(u, -n) = conj Delta(-u, n)).
-//  K2  ring sums D(r, n, x) of Eq. 9 as two pruned 1-D passes per side:
-//      rows |u_x| <= U_r along u_y, then columns along u_x.
+//  K2  ring sums D(r, n, x) of Eq. 9, per (side, column block): the row
+//      transform restricted to the block's columns as a pruned DFT over the
+//      ring's modes, then the column FFT over u_x in LDS.
 //  K3  triple-product sums S(c) = sum_x D D D of Eq. 8 for every kept
 //      combination, as MFMA 16x16x4 tiles: rows = (slot A, slot C) ring pairs,
 //      columns = slot-B rings, K = x_perp points staged through LDS.
@@ -105,65 +106,24 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
 }
 
 // ---------------------------------------------------------------- K2
-struct K2Line {
-  int32_t side;
-  int32_t ux;  // signed row
-};
-
-// Rows: for each listed (side, u_x), transform the ring-masked row of plane
-// n(side) along u_y into G[goff[side] + (u_x + U) * n + y].
+// Fused ring sums: block = (side s, tb consecutive columns y0..y0+tb-1).
+// Row transform restricted to the block's columns, straight from the ring's
+// modes (pruned DFT): G(u_x, y) = sum_{u_y : (u_x,u_y) in ring} Delta(u, n)
+// e^{-2 pi i u_y y / N}, then the column FFT over u_x in LDS, then D[s][x][y].
+// ring_mode_uy holds each ring's modes sorted by (u_x, u_y); ring_seg gives,
+// per ring, the start of every row u_x = -U..U (2U + 2 offsets from ring_seg_off[r]).
 template <typename T>
-__global__ __launch_bounds__(256) void k2_rows_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ G,
-                                                      const K2Line* __restrict__ lines, long n_lines,
-                                                      const int32_t* __restrict__ side_ring,
-                                                      const int32_t* __restrict__ side_plane,
-                                                      const int32_t* __restrict__ side_u,
-                                                      const long* __restrict__ goff, long g_total,
-                                                      const int32_t* __restrict__ mode_ring, int lim, int nkeep,
-                                                      const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
+__global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ D,
+                                                       const int32_t* __restrict__ side_ring,
+                                                       const int32_t* __restrict__ side_plane,
+                                                       const int32_t* __restrict__ side_u,
+                                                       const int32_t* __restrict__ ring_seg_off,
+                                                       const int32_t* __restrict__ ring_seg,
+                                                       const int16_t* __restrict__ ring_mode_uy, int n_sides,
+                                                       int nkeep, const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
   const int n = sh.n;
-  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
-  cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b0 = tw_l + n;
-  cplx<T>* b1 = b0 + tb * ls;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
-  const long l0 = long(blockIdx.x) * tb;
-  const int cnt = int(min(long(tb), n_lines - l0));
-  const int b = blockIdx.y;
-  const cplx<T>* Fb = F + size_t(b) * nkeep * n * n;
-  const int side_len = 2 * lim + 1;
-  for (int q = threadIdx.x; q < cnt * n; q += blockDim.x) {
-    const int l = q / n, uyi = q - l * n;
-    const K2Line ln = lines[l0 + l];
-    const int uy = uyi <= n / 2 ? uyi : uyi - n;
-    cplx<T> v = {T(0), T(0)};
-    if (uy >= -lim && uy <= lim && mode_ring[(ln.ux + lim) * side_len + (uy + lim)] == side_ring[ln.side]) {
-      const int uxi = ln.ux < 0 ? ln.ux + n : ln.ux;
-      v = Fb[(size_t(side_plane[ln.side]) * n + uxi) * n + uyi];
-    }
-    b0[l * ls + uyi] = v;
-  }
-  __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, cnt, ls);
-  cplx<T>* Gb = G + size_t(b) * g_total;
-  for (int q = threadIdx.x; q < cnt * n; q += blockDim.x) {
-    const int l = q / n, y = q - l * n;
-    const K2Line ln = lines[l0 + l];
-    Gb[goff[ln.side] + size_t(ln.ux + side_u[ln.side]) * n + y] = res[l * ls + y];
-  }
-}
-
-// Columns: for side s = blockIdx.x / (n / tb) and tb consecutive y, transform
-// along u_x (rows |u_x| <= U stored in G, the rest zero) into D[b][s][x][y].
-template <typename T>
-__global__ __launch_bounds__(256) void k2_cols_kernel(const cplx<T>* __restrict__ G, cplx<T>* __restrict__ D,
-                                                      const int32_t* __restrict__ side_u,
-                                                      const long* __restrict__ goff, long g_total, int n_sides,
-                                                      const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
-  extern __shared__ char smem_raw[];
-  const int n = sh.n;
-  const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
+  const int ls = n + 1;
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw_l + n;
   cplx<T>* b1 = b0 + tb * ls;
@@ -172,14 +132,38 @@ __global__ __launch_bounds__(256) void k2_cols_kernel(const cplx<T>* __restrict_
   const int s = blockIdx.x / ytiles;
   const int y0 = (blockIdx.x % ytiles) * tb;
   const int b = blockIdx.y;
+  const int r = side_ring[s];
   const int U = side_u[s];
-  const cplx<T>* Gs = G + size_t(b) * g_total + goff[s];
-  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
-    const int i = q / tb, l = q - i * tb;  // i = u_x index (mod n)
-    const int ux = i <= n / 2 ? i : i - n;
-    cplx<T> v = {T(0), T(0)};
-    if (ux >= -U && ux <= U) v = Gs[size_t(ux + U) * n + y0 + l];
-    b0[l * ls + i] = v;
+  const cplx<T>* Fp = F + (size_t(b) * nkeep + side_plane[s]) * size_t(n) * n;
+  const int32_t* seg = ring_seg + ring_seg_off[r - 1];
+  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) b0[(q / n) * ls + (q % n)] = {T(0), T(0)};
+  __syncthreads();
+  const int nrow = 2 * U + 1;
+  const float inv_n = 1.0f / float(n);
+  for (int q = threadIdx.x; q < nrow * tb; q += blockDim.x) {
+    const int row = q / tb, l = q - row * tb;
+    const int ux = row - U;
+    const int y = y0 + l;
+    const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + n : ux) * n;
+    cplx<T> acc0 = {T(0), T(0)}, acc1 = {T(0), T(0)};
+    const int m0 = seg[row], m1 = seg[row + 1];
+    int m = m0;
+    // (u_y y) mod n without an integer division: u_y y < 2^18, exact in float32 after correction
+    auto term = [&](int mm) {
+      const int uy = ring_mode_uy[mm];
+      const int uyi = uy < 0 ? uy + n : uy;
+      const int t = uyi * y;
+      int e = t - int(float(t) * inv_n) * n;
+      e += e < 0 ? n : 0;
+      e -= e >= n ? n : 0;
+      return cmul(Frow[uyi], tw_l[e]);
+    };
+    for (; m + 1 < m1; m += 2) {
+      acc0 = cadd(acc0, term(m));
+      acc1 = cadd(acc1, term(m + 1));
+    }
+    if (m < m1) acc0 = cadd(acc0, term(m));
+    b0[l * ls + (ux < 0 ? ux + n : ux)] = cadd(acc0, acc1);
   }
   __syncthreads();
   cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
