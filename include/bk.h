@@ -122,6 +122,20 @@ bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
  * forward FFT, ring FFTs, triple products, binning (hipEvents on the stream). */
 bk_status bk_get_stage_times(bk_plan plan, double* ms, size_t cap);
 
+/* Tile autotuning.  With a grid loaded, times every valid tile choice of the
+ * three tiled stages on hip_stream (lines per block of the forward FFT 2..16,
+ * columns per block of the ring sums 2..16, staged slots per chunk of the
+ * triple products 16..64, each within its LDS limit) and keeps the fastest of
+ * each; the results do not depend on these choices beyond rounding order.
+ * The choice is cached in the process per (N_g, precision, device, number of
+ * sides, number of workgroups), and later plans with the same key start from
+ * it.  Blocks until the timing is done.  On return the plan holds a complete
+ * estimate of the loaded grid (stage times included).  choices, if not NULL,
+ * receives int32 [3]: FFT lines, ring-sum columns, slots per chunk.  Errors:
+ * BK_ERR_STATE with no grid loaded, BK_ERR_HIP from a failed launch (the
+ * previous choices are then kept). */
+bk_status bk_plan_autotune(bk_plan plan, void* hip_stream, int* choices);
+
 /* A group of plans on one device (for example fields of different N_g, each
  * plan batched) estimated together.  On the first bk_group_estimate the
  * kernels of every plan are captured into one hipGraph with one branch per

@@ -71,6 +71,7 @@ _SIGS = {
     "bk_get_bin_means": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
     "bk_get_plan_info": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
     "bk_get_stage_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+    "bk_plan_autotune": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)],
     "bk_debug_get_buffer": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                             ctypes.POINTER(ctypes.c_size_t)],
     "bk_debug_mfma_probe": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
@@ -188,6 +189,12 @@ def bk_get_stage_times(plan: int) -> list:
     return out.tolist()
 
 
+def bk_plan_autotune(plan: int, stream: int = 0) -> list:
+    out = (ctypes.c_int * 3)()
+    _check(lib().bk_plan_autotune(ctypes.c_void_p(plan), ctypes.c_void_p(stream), out))
+    return list(out)
+
+
 def bk_count_triangles(binning: bk_binning):
     n = binning.n_k1 * binning.n_mu * binning.n_t
     out = np.empty(n, dtype=np.int64)
@@ -290,3 +297,6 @@ class Estimator:
 
     def stage_times(self) -> list:
         return bk_get_stage_times(self.plan)
+
+    def autotune(self, stream: int = 0) -> list:
+        return bk_plan_autotune(self.plan, stream)

@@ -2,11 +2,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <vector>
@@ -69,6 +73,9 @@ struct bk_plan_s {
   double delta_scale = 1.0;
   size_t lds_k3 = 0;
   int item_out = 512;     // float64 outputs per work item
+  int fft_tb = 0;         // lines per block of the K1 passes (0 = default)
+  int k2_tb = 0;          // columns per block of the ring sums (0 = default)
+  int tuned = 0;          // tile choices came from bk_plan_autotune
   int k3_chunk = 32;
   size_t bytes = 0;
 
@@ -98,6 +105,19 @@ struct bk_plan_s {
   hipEvent_t ev[5] = {};
   bool have_events = false;
 };
+
+namespace {
+
+// Tuned tile choices, cached per (N_g, precision, device, sides, workgroups).
+typedef std::tuple<int, int, int, long, long> TuneKey;
+std::mutex g_tune_mutex;
+std::map<TuneKey, std::array<int, 3>> g_tune_cache;
+
+TuneKey tune_key(bk_plan p) {
+  return TuneKey(p->sh.n, p->prec, p->device, p->n_sides, long(p->tab.groups.size()));
+}
+
+}  // namespace
 
 namespace {
 
@@ -141,6 +161,18 @@ constexpr bool prec_is_f32() {
   return sizeof(T) == 4;
 }
 
+// LDS bytes of the contraction for a chunk of ch points, 0 if the chunk does
+// not divide X or exceeds 64 KiB / the per-thread load budget.
+size_t k3_lds_bytes(const bk::Tables& T, int prec, long X, int ch) {
+  const size_t cs = prec == BK_F32 ? 8 : 16;
+  if (X % ch != 0) return 0;
+  const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
+  const size_t lds = size_t(T.max_group_sides) * slot;
+  const long loads = long(T.max_group_sides - 1) * (ch / int(16 / cs));
+  if (lds > 65536 || loads > long(bk::kK3MaxLoads) * bk::kK3Threads) return 0;
+  return lds;
+}
+
 // LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
 size_t fft_lds_bytes(int n, int tb, size_t elem_bytes) { return (size_t(n) + size_t(2) * tb * (n + 1)) * elem_bytes; }
 
@@ -157,7 +189,7 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   const int n = p->sh.n;
   const int B = p->batch;
   const size_t cs = sizeof(C);
-  const int tb = pick_tb(n, cs);
+  const int tb = p->fft_tb > 0 ? p->fft_tb : pick_tb(n, cs);
   const size_t lds_fft = fft_lds_bytes(n, tb, cs);
   const C* tw = reinterpret_cast<const C*>(p->d_tw);
   C* F = reinterpret_cast<C*>(p->d_F);
@@ -185,8 +217,7 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   // K2: ring sums, pruned row DFT + column FFT per (side, column block)
   if (p->n_sides > 0) {
     // columns per block: 8 (float32) or 4 (float64), i.e. 64-byte row segments and ~35 KiB of LDS
-    int tb2 = std::min(tb, prec_is_f32<T>() ? 8 : 4);
-    if (const char* v = std::getenv("BK_K2_TB")) tb2 = std::atoi(v);
+    int tb2 = p->k2_tb > 0 ? p->k2_tb : std::min(pick_tb(n, cs), prec_is_f32<T>() ? 8 : 4);
     dim3 g2(p->n_sides * (n / tb2), B);
     hipLaunchKernelGGL((bk::k2_fused_kernel<T>), g2, dim3(256), fft_lds_bytes(n, tb2, cs), st, F, D, p->d_side_ring,
                        p->d_side_plane, p->d_side_u, p->d_ring_seg_off, p->d_ring_seg, p->d_ring_mode_uy,
@@ -455,11 +486,8 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
     // largest chunk whose staging fits 64 KiB of LDS and the per-thread load budget
     p->k3_chunk = 0;
     for (int ch : {64, 32, 16}) {
-      if (X_ % ch != 0) continue;
-      const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
-      const size_t lds = size_t(T.max_group_sides) * slot;
-      const long loads = long(T.max_group_sides - 1) * (ch / int(16 / cs));
-      if (lds <= 65536 && loads <= long(bk::kK3MaxLoads) * bk::kK3Threads) {
+      const size_t lds = k3_lds_bytes(T, prec, X_, ch);
+      if (lds) {
         p->k3_chunk = ch;
         p->lds_k3 = lds;
         break;
@@ -469,6 +497,17 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
       release(p);
       delete p;
       return fail(BK_ERR_ARG, "workgroup staging exceeds 64 KiB of LDS or the per-thread load budget");
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    auto it = g_tune_cache.find(tune_key(p));
+    if (it != g_tune_cache.end() && k3_lds_bytes(T, prec, p->X, it->second[2])) {
+      p->fft_tb = it->second[0];
+      p->k2_tb = it->second[1];
+      p->k3_chunk = it->second[2];
+      p->lds_k3 = k3_lds_bytes(T, prec, p->X, p->k3_chunk);
+      p->tuned = 1;
     }
   }
   for (auto& e : p->ev) {
@@ -825,3 +864,74 @@ bk_status bk_group_destroy(bk_group g) {
 }
 
 }  // extern "C"
+
+
+extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  if (p->batch < 1) return fail(BK_ERR_STATE, "load a grid before tuning");
+  BK_HIP(hipSetDevice(p->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const int n = p->sh.n;
+  const size_t cs = 2 * p->elem;
+  std::vector<int> c_fft, c_k2, c_k3;
+  for (int tb : {2, 4, 8, 16})
+    if (n % tb == 0 && fft_lds_bytes(n, tb, cs) <= 73728) {
+      c_fft.push_back(tb);
+      c_k2.push_back(tb);
+    }
+  for (int ch : {16, 32, 64})
+    if (k3_lds_bytes(p->tab, p->prec, p->X, ch)) c_k3.push_back(ch);
+  if (c_fft.empty() || c_k3.empty()) return fail(BK_ERR_ARG, "no valid tile choice to tune");
+  const int saved[3] = {p->fft_tb, p->k2_tb, p->k3_chunk};
+  const size_t saved_lds = p->lds_k3;
+  const size_t rounds = std::max({c_fft.size(), c_k2.size(), c_k3.size()});
+  std::vector<double> t_fft(c_fft.size(), 1e30), t_k2(c_k2.size(), 1e30), t_k3(c_k3.size(), 1e30);
+  // Stage times are independent of the other stages' tiles, so round i times
+  // candidate i of every stage at once; each configuration runs twice, the
+  // second run is kept.
+  for (size_t i = 0; i < rounds; ++i) {
+    p->fft_tb = c_fft[std::min(i, c_fft.size() - 1)];
+    p->k2_tb = c_k2[std::min(i, c_k2.size() - 1)];
+    p->k3_chunk = c_k3[std::min(i, c_k3.size() - 1)];
+    p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->X, p->k3_chunk);
+    for (int rep = 0; rep < 2; ++rep) {
+      bk_status sst = p->prec == BK_F32 ? launch_all<float>(p, st, true) : launch_all<double>(p, st, true);
+      if (sst != BK_OK) {
+        p->fft_tb = saved[0];
+        p->k2_tb = saved[1];
+        p->k3_chunk = saved[2];
+        p->lds_k3 = saved_lds;
+        return sst;
+      }
+    }
+    BK_HIP(hipEventSynchronize(p->ev[4]));
+    float ms[3];
+    for (int k = 0; k < 3; ++k) BK_HIP(hipEventElapsedTime(&ms[k], p->ev[k], p->ev[k + 1]));
+    if (i < c_fft.size()) t_fft[i] = ms[0];
+    if (i < c_k2.size()) t_k2[i] = ms[1];
+    if (i < c_k3.size()) t_k3[i] = ms[2];
+  }
+  auto best = [](const std::vector<int>& c, const std::vector<double>& t) {
+    return c[size_t(std::min_element(t.begin(), t.end()) - t.begin())];
+  };
+  p->fft_tb = best(c_fft, t_fft);
+  p->k2_tb = best(c_k2, t_k2);
+  p->k3_chunk = best(c_k3, t_k3);
+  p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->X, p->k3_chunk);
+  p->tuned = 1;
+  // the last configuration timed ran the whole path: its results stand
+  p->stream = st;
+  p->estimated = 1;
+  p->timed = 1;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[tune_key(p)] = {p->fft_tb, p->k2_tb, p->k3_chunk};
+  }
+  if (choices) {
+    choices[0] = p->fft_tb;
+    choices[1] = p->k2_tb;
+    choices[2] = p->k3_chunk;
+  }
+  return BK_OK;
+}

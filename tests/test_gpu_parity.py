@@ -245,3 +245,47 @@ def test_stage_buffers_match_oracle(prec):
             assert np.abs(D[i] - Dref).max() < tol * max(np.abs(Dref).max(), 1e-300), (r, n)
     finally:
         est.close()
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_autotuned_plan_matches_oracle(prec):
+    """Every tile choice the tuner tries ends in a correct estimate; the tuned
+    plan, and a second plan picking the choice up from the cache, stay within
+    the parity bar, with identical triangle counts."""
+    torch = _torch()
+    from paper_2405_14513_amd import bk
+
+    args, recipe = CASES[2]
+    b, delta, ref = oracle_result(args, recipe)
+    binning = bk.make_binning(*args)
+    stream = torch.cuda.current_stream().cuda_stream
+    t = torch.from_numpy(delta).cuda()
+    _say(f"autotune N_g=48 prec={prec}")
+    est = bk.Estimator(binning, prec=prec)
+    est2 = None
+    try:
+        est.load(t, stream)
+        choices = est.autotune(stream)
+        assert choices[0] in (2, 4, 8, 16) and choices[1] in (2, 4, 8, 16) and choices[2] in (16, 32, 64)
+        err_tuned = per_multipole_error(est.multipoles()[0], ref.B)
+        est.estimate(stream)
+        err = per_multipole_error(est.multipoles()[0], ref.B)
+        assert np.array_equal(est.counts(), ref.counts)
+        assert err_tuned.max() < TOL[prec], err_tuned
+        assert err.max() < TOL[prec], err
+        est2 = bk.Estimator(binning, prec=prec)
+        est2.load(t, stream)
+        est2.estimate(stream)
+        err2 = per_multipole_error(est2.multipoles()[0], ref.B)
+        assert err2.max() < TOL[prec], err2
+    finally:
+        est.close()
+        if est2 is not None:
+            est2.close()
+    with pytest.raises(bk.BkError) as e:
+        fresh = bk.Estimator(binning, prec=prec)
+        try:
+            fresh.autotune(stream)
+        finally:
+            fresh.close()
+    assert e.value.status == bk.BK_ERR_STATE
