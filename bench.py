@@ -63,10 +63,11 @@ def read_traffic(ng):
         return None
 
 
-def time_path(bk, torch, binning, prec, field, steps, warmup):
+def time_path(bk, torch, binning, prec, field, steps, warmup, tune=True):
     est = bk.Estimator(binning, prec=prec)
     stream = torch.cuda.current_stream().cuda_stream
     est.load(field, stream)
+    choices = est.autotune(stream) if tune else None  # untimed, like plan creation
     for _ in range(warmup):
         est.estimate(stream)
     torch.cuda.synchronize()
@@ -82,6 +83,7 @@ def time_path(bk, torch, binning, prec, field, steps, warmup):
     ms = start.elapsed_time(end) / steps
     B = est.multipoles()[0]
     info = est.info()
+    info["tiles"] = choices
     est.close()
     return ms, stages, B, info
 
@@ -138,6 +140,7 @@ def run_batched(args, np, torch, bk, FieldRecipe, make_field):
         t = torch.from_numpy(f.astype(np.float32)).cuda()
         plan = bk.bk_plan_create(binning, bk.BK_F32, 0, count)
         bk.bk_load_grid(plan, t.data_ptr(), bk.BK_F32, count, True, stream)
+        bk.bk_plan_autotune(plan, stream)  # untimed; the graph captures the tuned tiles
         plans.append(plan)
         tensors.append(t)
         n_values += count * 20 * 10 * 10 * 16
@@ -193,6 +196,7 @@ def main():
                     help="time the uneven batch (24 x N_g=64, 24 x 96, 16 x 128, float32) as one graph launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile choices")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -219,7 +223,8 @@ def main():
     f32 = torch.from_numpy(delta64.astype(np.float32)).cuda()
     f64 = torch.from_numpy(delta64).cuda()
 
-    ms32, st32, B32, info = time_path(bk, torch, binning, bk.BK_F32, f32, args.steps, args.warmup)
+    ms32, st32, B32, info = time_path(bk, torch, binning, bk.BK_F32, f32, args.steps, args.warmup,
+                                      not args.no_autotune)
     n_values = wl["n_k1"] * wl["n_mu"] * wl["n_t"] * 16
     out = {
         "metric": METRIC,
@@ -264,12 +269,15 @@ def main():
         "avg_launch_ms": k3_ms,
     }
     out["plan"] = {k: info[k] for k in ("combinations", "work_items", "sides", "rings", "plane_triples")}
+    out["plan"]["tiles"] = info["tiles"]  # [FFT lines, ring-sum columns, slots per chunk]
     if not args.no_fp64:
-        ms64, st64, B64, _ = time_path(bk, torch, binning, bk.BK_F64, f64, args.steps, args.warmup)
+        ms64, st64, B64, info64 = time_path(bk, torch, binning, bk.BK_F64, f64, args.steps, args.warmup,
+                                            not args.no_autotune)
         out["fp64"] = {
             "ms_per_step": ms64,
             "value": n_values / (ms64 * 1e-3),
             "stage_ms": {k: float(np.mean([s[i] for s in st64])) for i, k in enumerate(stage_names)},
+            "tiles": info64["tiles"],
         }
         out["fp32_vs_fp64_speedup"] = ms64 / ms32
     gold = os.path.join(ROOT, "tests", "golden", f"oracle_ng{ng}.npz")

@@ -11,6 +11,14 @@
  *   N_tri(c)      number of closed (u, v, w) in the three rings             (Eq. 10)
  *   B_l^m(bin)    sqrt((2l+1)/4pi) sum Y* B_hat N_tri / sum |Y|^2 N_tri     (Eq. 13)
  *
+ * The sum over x in Eq. 8 only has to resolve wave vectors that close:
+ * modes of the three rings reach |u_x|, |u_y| <= U_1, U_2, U_3, so on an
+ * m x m grid with m > U_1 + U_2 + U_3 the only closure mod m is the exact one,
+ * and S on that grid is (m / N_g)^2 times S on the N_g grid.  Each
+ * combination is summed on the smallest such grid of size 2^a or 3 * 2^a
+ * (>= 16, and > 2 max U so D needs no wrapped modes), with D evaluated on
+ * that grid: the same result, up to rounding, at a fraction of the points.
+ *
  * Conventions (the paper leaves these open; the library fixes them):
  *   - wave vectors are integer lattice vectors, k in units of k_f = 2 pi / L;
  *     z (the fastest grid index) is the line of sight;
@@ -75,7 +83,9 @@ typedef struct {
  * host and allocate the device working set on `device` for up to `max_batch`
  * fields of this size.  prec selects float32 (BK_F32: FFTs, D and the products
  * in float32, blocked float32 partial sums combined in float64) or float64
- * (BK_F64: every step in float64).  The final per-bin sums are float64 in both. */
+ * (BK_F64: every step in float64).  The final per-bin sums are float64 in both.
+ * Setting the environment variable BK_FULL_GRID=1 sums every combination on
+ * the full N_g x N_g grid instead (same results up to rounding; slower). */
 bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int max_batch, bk_plan* out);
 bk_status bk_plan_destroy(bk_plan plan);
 
@@ -112,10 +122,13 @@ bk_status bk_get_triangle_counts(bk_plan plan, int64_t* out, size_t cap);
 /* N_tri-weighted mean (k1, mu, t) of each bin, float64 [n_bins][3]; NaN if empty. */
 bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
 
-/* Plan statistics, float64 [9]: combinations (an n -> -n partner pair counted
- * once), work items, sides, rings, dense products per field (contraction
- * terms incl. padding), useful products, device bytes held, number of
- * canonical plane triples, combinations that are their own partner. */
+/* Plan statistics, float64 [cap] with 9 <= cap (11 filled at most):
+ * combinations (an n -> -n partner pair counted once), work items, sides,
+ * rings, dense products per field (contraction terms incl. padding, summed
+ * over each combination's grid points), useful products (combinations x their
+ * grid points), device bytes held, number of canonical plane triples,
+ * combinations that are their own partner, grid sides (a side evaluated on
+ * one grid size), complex elements of D per field. */
 bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
 
 /* Device time of each stage of the last estimate in milliseconds, float64 [4]:
@@ -157,9 +170,10 @@ bk_status bk_count_triangles(const bk_binning* binning, int64_t* out, size_t cap
 
 /* Test support: copy an intermediate device buffer of the last estimate into
  * host memory.  which = 0: Delta planes, complex [batch][nkeep][N][N] (scaled
- * by N^-3/2, planes n = 0..nkeep-1, indices u mod N); 1: D of the stored sides
- * n >= 0, complex [batch][n_sides][N][N] (x_perp index x * N + y); 2: the
- * side table, int32 [n_sides][2] = (ring, n); 3, 4, 5: the contraction's work
+ * by N^-3/2, planes n = 0..nkeep-1, indices u mod N); 1: D of every grid side
+ * (a stored side n >= 0 on one grid size m), complex [batch][sum of m^2] with
+ * the grid sides one after the other, x_perp index x * m + y; 2: the grid-side
+ * table in that order, int32 [grid sides][3] = (ring, n, m); 3, 4, 5: the contraction's work
  * items, workgroups and staged-side lists as stored on the host (raw bytes).
  * Elements of 0 and 1 are float32 pairs for BK_F32 plans, float64 pairs for
  * BK_F64.  *needed receives the size in bytes; BK_ERR_SIZE if cap_bytes is

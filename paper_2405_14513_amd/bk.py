@@ -176,10 +176,10 @@ def bk_get_bin_means(plan: int) -> np.ndarray:
 
 
 def bk_get_plan_info(plan: int) -> dict:
-    out = np.empty(9, dtype=np.float64)
-    _check(lib().bk_get_plan_info(ctypes.c_void_p(plan), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 9))
+    out = np.empty(11, dtype=np.float64)
+    _check(lib().bk_get_plan_info(ctypes.c_void_p(plan), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 11))
     keys = ["combinations", "work_items", "sides", "rings", "dense_terms", "useful_terms", "device_bytes",
-            "plane_triples", "self_partnered"]
+            "plane_triples", "self_partnered", "grid_sides", "d_elems_per_field"]
     return dict(zip(keys, out.tolist()))
 
 

@@ -67,7 +67,6 @@ struct bk_plan_s {
   bk::FftShape sh{};
   int nkeep = 0;
   long n_sides = 0;
-  long X = 0;
   long n_items = 0;
   double norm = 0.0;
   double delta_scale = 1.0;
@@ -81,10 +80,15 @@ struct bk_plan_s {
 
   void* d_in = nullptr;       // [max_batch][N^3] of the input dtype
   void* d_F = nullptr;        // [max_batch][nkeep][N][N] complex
-  void* d_D = nullptr;        // [max_batch][n_sides][N^2] complex
+  void* d_D = nullptr;        // [max_batch][d_elems] complex: every grid side's m x m points
   double* d_S = nullptr;      // [max_batch][n_items][512]
   double* d_B = nullptr;      // [max_batch][n_lm][n_bins]
   void* d_tw = nullptr;       // twiddles, N complex
+  void* d_tw_lv = nullptr;    // twiddles of every grid level, m complex each, at tw_lv_off
+  std::vector<long> tw_lv_off;
+  std::vector<bk::FftShape> lv_sh;
+  int32_t* d_gs_side = nullptr;  // side of every grid side
+  int64_t* d_gs_off = nullptr;   // offset of every grid side in a field's D
   bk::GroupDesc* d_groups = nullptr;
   bk::ItemDesc* d_items = nullptr;
   int32_t* d_group_sides = nullptr;
@@ -149,7 +153,7 @@ void release(bk_plan p) {
                   p->d_side_ring,  p->d_side_plane, p->d_side_u,
                   p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty,
                   p->d_chunk_begin, p->d_bin_chunk, p->d_part,     p->d_ring_seg_off, p->d_ring_seg,
-                  p->d_ring_mode_uy};
+                  p->d_ring_mode_uy, p->d_tw_lv,   p->d_gs_side,  p->d_gs_off};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->have_events)
@@ -162,10 +166,12 @@ constexpr bool prec_is_f32() {
 }
 
 // LDS bytes of the contraction for a chunk of ch points, 0 if the chunk does
-// not divide X or exceeds 64 KiB / the per-thread load budget.
-size_t k3_lds_bytes(const bk::Tables& T, int prec, long X, int ch) {
+// not divide every grid level's m^2 points or exceeds 64 KiB / the per-thread
+// load budget.
+size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
   const size_t cs = prec == BK_F32 ? 8 : 16;
-  if (X % ch != 0) return 0;
+  for (int m : T.grid_sizes)
+    if ((long(m) * m) % ch != 0) return 0;
   const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
   const size_t lds = size_t(T.max_group_sides) * slot;
   const long loads = long(T.max_group_sides - 1) * (ch / int(16 / cs));
@@ -175,6 +181,13 @@ size_t k3_lds_bytes(const bk::Tables& T, int prec, long X, int ch) {
 
 // LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
 size_t fft_lds_bytes(int n, int tb, size_t elem_bytes) { return (size_t(n) + size_t(2) * tb * (n + 1)) * elem_bytes; }
+
+// The largest power of two <= want that divides m and keeps the FFT LDS within 72 KiB.
+int fit_tb(int m, int want, size_t elem_bytes) {
+  int tb = 1;
+  while (tb * 2 <= want && m % (tb * 2) == 0 && fft_lds_bytes(m, tb * 2, elem_bytes) <= 73728) tb *= 2;
+  return tb;
+}
 
 int pick_tb(int n, size_t elem_bytes) {
   // lines per block: at most 16, dividing n, LDS at most 72 KiB (two blocks per CU)
@@ -214,24 +227,32 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
-  // K2: ring sums, pruned row DFT + column FFT per (side, column block)
-  if (p->n_sides > 0) {
-    // columns per block: 8 (float32) or 4 (float64), i.e. 64-byte row segments and ~35 KiB of LDS
-    int tb2 = p->k2_tb > 0 ? p->k2_tb : std::min(pick_tb(n, cs), prec_is_f32<T>() ? 8 : 4);
-    dim3 g2(p->n_sides * (n / tb2), B);
-    hipLaunchKernelGGL((bk::k2_fused_kernel<T>), g2, dim3(256), fft_lds_bytes(n, tb2, cs), st, F, D, p->d_side_ring,
-                       p->d_side_plane, p->d_side_u, p->d_ring_seg_off, p->d_ring_seg, p->d_ring_mode_uy,
-                       int(p->n_sides), p->nkeep, tw, p->sh, tb2);
-    BK_HIP(hipGetLastError());
+  // K2: ring sums, pruned row DFT + column FFT per (grid side, column block), one launch per grid level
+  {
+    const C* twl = reinterpret_cast<const C*>(p->d_tw_lv);
+    const auto& lvb = p->tab.level_gside_begin;
+    for (size_t L = 0; L + 1 < lvb.size(); ++L) {
+      const int n_gs = lvb[L + 1] - lvb[L];
+      if (n_gs == 0) continue;
+      const int m = p->tab.grid_sizes[L];
+      // columns per block: 8 (float32) or 4 (float64) by default, i.e. 64-byte row segments
+      const int tb2 = fit_tb(m, p->k2_tb > 0 ? p->k2_tb : (prec_is_f32<T>() ? 8 : 4), cs);
+      dim3 g2(n_gs * (m / tb2), B);
+      hipLaunchKernelGGL((bk::k2_fused_kernel<T>), g2, dim3(256), fft_lds_bytes(m, tb2, cs), st, F, D, p->d_gs_side,
+                         p->d_gs_off, lvb[L], long(p->tab.d_elems), p->d_side_ring, p->d_side_plane, p->d_side_u,
+                         p->d_ring_seg_off, p->d_ring_seg, p->d_ring_mode_uy, n, p->nkeep, twl + p->tw_lv_off[L],
+                         p->lv_sh[L], tb2);
+      BK_HIP(hipGetLastError());
+    }
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[2], st));
   // K3: triple products
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
-    const int ng = int(p->tab.groups.size());
 #define BK_K3(CHV, TV)                                                                                          \
-  hipLaunchKernelGGL((bk::k3_contract_kernel<T, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D, p->n_sides, \
-                     p->d_groups, ng, p->d_items, p->d_group_sides, p->X, p->d_S, p->n_items)
+  hipLaunchKernelGGL((bk::k3_contract_kernel<T, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,            \
+                     long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides, p->d_S,           \
+                     p->n_items)
     const int tiles = p->tab.k3.pairs_per_item / 16;
     if (p->k3_chunk == 64 && tiles == 2)
       BK_K3(64, 2);
@@ -359,6 +380,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   bk::K3Shape shape;
   shape.pairs_per_item = prec == BK_F32 ? 32 : 64;
   if (const char* v = std::getenv("BK_K3_PAIRS")) shape.pairs_per_item = std::atoi(v);
+  if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
   try {
     err = bk::build_tables(b, shape, host_threads(), &p->tab);
@@ -372,8 +394,6 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   }
   bk::Tables& T = p->tab;
   const int n = bn->ng;
-  p->X = long(n) * n;
-  const long X_ = p->X;
   p->nkeep = T.nmax + 1;
   if (p->nkeep > n / 2 + 1) p->nkeep = n / 2 + 1;
   p->n_sides = long(T.side_ring.size());
@@ -439,7 +459,29 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(put(p, &p->d_ring_seg_off, ring_seg_off.data(), ring_seg_off.size()));
   TRY(put(p, &p->d_ring_seg, ring_seg.data(), ring_seg.size()));
   TRY(put(p, &p->d_ring_mode_uy, ring_mode_uy.data(), ring_mode_uy.size()));
-  TRY(dalloc(p, &p->d_D, size_t(max_batch) * size_t(p->n_sides) * size_t(p->X) * cs));
+  TRY(dalloc(p, &p->d_D, size_t(max_batch) * size_t(T.d_elems) * cs));
+  {
+    // twiddles e^{-2 pi i t / m} of every grid level, concatenated
+    std::vector<double> tl;
+    for (int m : T.grid_sizes) {
+      bk::FftShape lsh{};
+      fft_shape(m, &lsh);
+      p->lv_sh.push_back(lsh);
+      p->tw_lv_off.push_back(long(tl.size() / 2));
+      for (int t = 0; t < m; ++t) {
+        tl.push_back(std::cos(2.0 * M_PI * double(t) / double(m)));
+        tl.push_back(-std::sin(2.0 * M_PI * double(t) / double(m)));
+      }
+    }
+    if (prec == BK_F32) {
+      std::vector<float> tf(tl.begin(), tl.end());
+      TRY(put(p, reinterpret_cast<float**>(&p->d_tw_lv), tf.data(), tf.size()));
+    } else {
+      TRY(put(p, reinterpret_cast<double**>(&p->d_tw_lv), tl.data(), tl.size()));
+    }
+  }
+  TRY(put(p, &p->d_gs_side, T.gside_side.data(), T.gside_side.size()));
+  TRY(put(p, &p->d_gs_off, T.gside_off.data(), T.gside_off.size()));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * p->item_out * 8));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_B), size_t(max_batch) * nlm * n_bins * 8));
   if (prec == BK_F32)
@@ -486,7 +528,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
     // largest chunk whose staging fits 64 KiB of LDS and the per-thread load budget
     p->k3_chunk = 0;
     for (int ch : {64, 32, 16}) {
-      const size_t lds = k3_lds_bytes(T, prec, X_, ch);
+      const size_t lds = k3_lds_bytes(T, prec, ch);
       if (lds) {
         p->k3_chunk = ch;
         p->lds_k3 = lds;
@@ -502,11 +544,11 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     auto it = g_tune_cache.find(tune_key(p));
-    if (it != g_tune_cache.end() && k3_lds_bytes(T, prec, p->X, it->second[2])) {
+    if (it != g_tune_cache.end() && k3_lds_bytes(T, prec, it->second[2])) {
       p->fft_tb = it->second[0];
       p->k2_tb = it->second[1];
       p->k3_chunk = it->second[2];
-      p->lds_k3 = k3_lds_bytes(T, prec, p->X, p->k3_chunk);
+      p->lds_k3 = k3_lds_bytes(T, prec, p->k3_chunk);
       p->tuned = 1;
     }
   }
@@ -630,7 +672,7 @@ bk_status bk_get_bin_means(bk_plan p, double* out, size_t cap) {
 bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
   g_last_error.clear();
   if (!p || !info) return fail(BK_ERR_ARG, "null argument");
-  if (cap < 9) return fail(BK_ERR_SIZE, "info buffer needs 9 entries");
+  if (cap < 9) return fail(BK_ERR_SIZE, "info buffer needs at least 9 entries");
   info[0] = double(p->tab.n_combos);
   info[1] = double(p->n_items);
   info[2] = double(p->n_sides);
@@ -640,6 +682,8 @@ bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
   info[6] = double(p->bytes);
   info[7] = double(p->tab.n_canonical_planes);
   info[8] = double(p->tab.n_self_partner);
+  if (cap > 9) info[9] = double(p->tab.gside_side.size());
+  if (cap > 10) info[10] = double(p->tab.d_elems);
   return BK_OK;
 }
 
@@ -670,12 +714,14 @@ bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes,
     bytes = size_t(p->batch) * p->nkeep * n2 * cs;
     src = p->d_F;
   } else if (which == 1) {
-    bytes = size_t(p->batch) * size_t(p->n_sides) * n2 * cs;
+    bytes = size_t(p->batch) * size_t(p->tab.d_elems) * cs;
     src = p->d_D;
   } else if (which == 2) {
-    for (long s = 0; s < p->n_sides; ++s) {
+    for (size_t g = 0; g < p->tab.gside_side.size(); ++g) {
+      const int32_t s = p->tab.gside_side[g];
       table.push_back(p->tab.side_ring[s]);
       table.push_back(p->tab.side_plane[s]);
+      table.push_back(p->tab.grid_sizes[p->tab.gside_level[g]]);
     }
     bytes = table.size() * sizeof(int32_t);
   } else if (which == 3) {
@@ -881,7 +927,7 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
       c_k2.push_back(tb);
     }
   for (int ch : {16, 32, 64})
-    if (k3_lds_bytes(p->tab, p->prec, p->X, ch)) c_k3.push_back(ch);
+    if (k3_lds_bytes(p->tab, p->prec, ch)) c_k3.push_back(ch);
   if (c_fft.empty() || c_k3.empty()) return fail(BK_ERR_ARG, "no valid tile choice to tune");
   const int saved[3] = {p->fft_tb, p->k2_tb, p->k3_chunk};
   const size_t saved_lds = p->lds_k3;
@@ -894,7 +940,7 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
     p->fft_tb = c_fft[std::min(i, c_fft.size() - 1)];
     p->k2_tb = c_k2[std::min(i, c_k2.size() - 1)];
     p->k3_chunk = c_k3[std::min(i, c_k3.size() - 1)];
-    p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->X, p->k3_chunk);
+    p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->k3_chunk);
     for (int rep = 0; rep < 2; ++rep) {
       bk_status sst = p->prec == BK_F32 ? launch_all<float>(p, st, true) : launch_all<double>(p, st, true);
       if (sst != BK_OK) {
@@ -918,7 +964,7 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
   p->fft_tb = best(c_fft, t_fft);
   p->k2_tb = best(c_k2, t_k2);
   p->k3_chunk = best(c_k3, t_k3);
-  p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->X, p->k3_chunk);
+  p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->k3_chunk);
   p->tuned = 1;
   // the last configuration timed ran the whole path: its results stand
   p->stream = st;

@@ -106,71 +106,77 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
 }
 
 // ---------------------------------------------------------------- K2
-// Fused ring sums: block = (side s, tb consecutive columns y0..y0+tb-1).
-// Row transform restricted to the block's columns, straight from the ring's
-// modes (pruned DFT): G(u_x, y) = sum_{u_y : (u_x,u_y) in ring} Delta(u, n)
-// e^{-2 pi i u_y y / N}, then the column FFT over u_x in LDS, then D[s][x][y].
+// Fused ring sums on one grid level of size m (sh.n): block = (grid side gs,
+// tb consecutive columns y0..y0+tb-1).  Row transform restricted to the
+// block's columns, straight from the ring's modes (pruned DFT):
+// G(u_x, y) = sum_{u_y : (u_x,u_y) in ring} Delta(u, n) e^{-2 pi i u_y y / m},
+// then the column FFT over u_x (placed at u_x mod m) in LDS, then D at
+// gside_off[gs] + x m + y.  Delta is read from the N_g-point planes.  Every
+// ring reaching this level has 2 U < m, so no two modes share a position.
 // ring_mode_uy holds each ring's modes sorted by (u_x, u_y); ring_seg gives,
 // per ring, the start of every row u_x = -U..U (2U + 2 offsets from ring_seg_off[r]).
 template <typename T>
 __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ D,
-                                                       const int32_t* __restrict__ side_ring,
+                                                       const int32_t* __restrict__ gside_side,
+                                                       const int64_t* __restrict__ gside_off, int gs_begin,
+                                                       long d_elems, const int32_t* __restrict__ side_ring,
                                                        const int32_t* __restrict__ side_plane,
                                                        const int32_t* __restrict__ side_u,
                                                        const int32_t* __restrict__ ring_seg_off,
                                                        const int32_t* __restrict__ ring_seg,
-                                                       const int16_t* __restrict__ ring_mode_uy, int n_sides,
-                                                       int nkeep, const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
+                                                       const int16_t* __restrict__ ring_mode_uy, int ng, int nkeep,
+                                                       const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
-  const int n = sh.n;
-  const int ls = n + 1;
+  const int m = sh.n;
+  const int ls = m + 1;
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b0 = tw_l + n;
+  cplx<T>* b0 = tw_l + m;
   cplx<T>* b1 = b0 + tb * ls;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_l[i] = tw[i];
-  const int ytiles = n / tb;
-  const int s = blockIdx.x / ytiles;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) tw_l[i] = tw[i];
+  const int ytiles = m / tb;
+  const int gs = gs_begin + int(blockIdx.x) / ytiles;
   const int y0 = (blockIdx.x % ytiles) * tb;
   const int b = blockIdx.y;
+  const int s = gside_side[gs];
   const int r = side_ring[s];
   const int U = side_u[s];
-  const cplx<T>* Fp = F + (size_t(b) * nkeep + side_plane[s]) * size_t(n) * n;
+  const cplx<T>* Fp = F + (size_t(b) * nkeep + side_plane[s]) * size_t(ng) * ng;
   const int32_t* seg = ring_seg + ring_seg_off[r - 1];
-  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) b0[(q / n) * ls + (q % n)] = {T(0), T(0)};
+  for (int q = threadIdx.x; q < tb * m; q += blockDim.x) b0[(q / m) * ls + (q % m)] = {T(0), T(0)};
   __syncthreads();
   const int nrow = 2 * U + 1;
-  const float inv_n = 1.0f / float(n);
+  const float inv_m = 1.0f / float(m);
   for (int q = threadIdx.x; q < nrow * tb; q += blockDim.x) {
     const int row = q / tb, l = q - row * tb;
     const int ux = row - U;
     const int y = y0 + l;
-    const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + n : ux) * n;
+    const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + ng : ux) * ng;
     cplx<T> acc0 = {T(0), T(0)}, acc1 = {T(0), T(0)};
     const int m0 = seg[row], m1 = seg[row + 1];
-    int m = m0;
-    // (u_y y) mod n without an integer division: u_y y < 2^18, exact in float32 after correction
-    auto term = [&](int mm) {
-      const int uy = ring_mode_uy[mm];
-      const int uyi = uy < 0 ? uy + n : uy;
-      const int t = uyi * y;
-      int e = t - int(float(t) * inv_n) * n;
-      e += e < 0 ? n : 0;
-      e -= e >= n ? n : 0;
-      return cmul(Frow[uyi], tw_l[e]);
+    int k = m0;
+    // (u_y y) mod m without an integer division: u_y y < 2^18, exact in float32 after correction
+    auto term = [&](int kk) {
+      const int uy = ring_mode_uy[kk];
+      const int uyf = uy < 0 ? uy + ng : uy;
+      const int t = (uy < 0 ? uy + m : uy) * y;
+      int e = t - int(float(t) * inv_m) * m;
+      e += e < 0 ? m : 0;
+      e -= e >= m ? m : 0;
+      return cmul(Frow[uyf], tw_l[e]);
     };
-    for (; m + 1 < m1; m += 2) {
-      acc0 = cadd(acc0, term(m));
-      acc1 = cadd(acc1, term(m + 1));
+    for (; k + 1 < m1; k += 2) {
+      acc0 = cadd(acc0, term(k));
+      acc1 = cadd(acc1, term(k + 1));
     }
-    if (m < m1) acc0 = cadd(acc0, term(m));
-    b0[l * ls + (ux < 0 ? ux + n : ux)] = cadd(acc0, acc1);
+    if (k < m1) acc0 = cadd(acc0, term(k));
+    b0[l * ls + (ux < 0 ? ux + m : ux)] = cadd(acc0, acc1);
   }
   __syncthreads();
   cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
-  cplx<T>* Ds = D + (size_t(b) * n_sides + s) * size_t(n) * n;
-  for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
+  cplx<T>* Ds = D + size_t(b) * d_elems + gside_off[gs];
+  for (int q = threadIdx.x; q < tb * m; q += blockDim.x) {
     const int x = q / tb, l = q - x * tb;
-    Ds[size_t(x) * n + y0 + l] = res[l * ls + x];
+    Ds[size_t(x) * m + y0 + l] = res[l * ls + x];
   }
 }
 
@@ -220,22 +226,23 @@ struct K3Lds {
 constexpr int kK3Threads = 64 * kItemsPerGroup;
 constexpr int kK3MaxLoads = 8;  // 16-byte global loads per thread per chunk
 
-// One block = one GroupDesc (all on one canonical plane triple), one wave per
-// work item of 16 * TILES ring pairs x 16 slot-B rings.  Every CH points of
-// x_perp the block stages the group's sides into LDS (16-byte loads, the next
+// One block = one GroupDesc (all on one canonical plane triple and one grid
+// of m x m points), one wave per work item of 16 * TILES ring pairs x 16
+// slot-B rings.  Every CH points of x_perp the block stages the group's sides into LDS (16-byte loads, the next
 // chunk prefetched into registers while the current one is consumed); each
 // wave then forms the pair products P = D_A conj(D_C) (4 points per lane
 // group) and feeds Re P, -Im P against Re D_B, Im D_B into 16x16x4 MFMAs
 // (K = 4 points), one accumulator per row tile.  The chunk's partial sums are
-// added to float64 registers.  Blocks are visited XCD by XCD: consecutive
-// block ids go to different XCDs, so block id q*8 + x runs group
-// x*ceil(G/8) + q and each XCD's L2 serves consecutive groups, which share
-// plane triples.
+// added to float64 registers.  Groups come largest grid first and, within a
+// grid, in plane-triple order: the dispatcher deals consecutive blocks to the
+// eight XCDs in turn, so every XCD gets an even share of each grid size, and
+// groups that read the same sides run at about the same time.
 template <typename T, int CH, int TILES>
-__global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long n_sides_total,
-                                                                 const GroupDesc* __restrict__ groups, int n_groups,
+__global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
+                                                                 const int64_t* __restrict__ gside_off,
+                                                                 const GroupDesc* __restrict__ groups,
                                                                  const ItemDesc* __restrict__ items,
-                                                                 const int32_t* __restrict__ group_sides, long X,
+                                                                 const int32_t* __restrict__ group_sides,
                                                                  double* __restrict__ S_out, long n_items_total) {
   using L = K3Lds<T, CH>;
   constexpr int kOut = 16 * TILES * kTileN;
@@ -243,19 +250,14 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   extern __shared__ char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   T* ldsr = reinterpret_cast<T*>(smem_raw);  // split layout view
-  int gid;
-  {
-    const int bid = blockIdx.x, xcd = bid & 7, q = bid >> 3;
-    const int Q = n_groups >> 3, R = n_groups & 7;
-    gid = xcd < R ? xcd * (Q + 1) + q : R * (Q + 1) + (xcd - R) * Q + q;
-  }
-  const GroupDesc gd = groups[gid];
+  const GroupDesc gd = groups[blockIdx.x];
   const int b = blockIdx.y;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int row = lane & 15;
   const int kq = lane >> 4;
-  const cplx<T>* Db = D + size_t(b) * n_sides_total * X;
+  const cplx<T>* Db = D + size_t(b) * d_elems;
+  const long X = long(gd.grid) * gd.grid;  // the group's grid points (a multiple of CH)
 
   // zero slot
   if constexpr (L::split) {
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     const int q = threadIdx.x + i * kK3Threads;
     const int qq = q < n_loads ? q : 0;
     const int sl = qq / L::per_side, v = qq - sl * L::per_side;
-    src[i] = reinterpret_cast<const v16*>(Db + size_t(group_sides[gd.side_begin + sl]) * X + v * L::vec);
+    src[i] = reinterpret_cast<const v16*>(Db + gside_off[group_sides[gd.side_begin + sl]] + v * L::vec);
     dst[i] = sl * L::stride + v * L::vec;
   }
   v16 stage[kK3MaxLoads];

@@ -10,7 +10,9 @@
 #include <atomic>
 #include <cmath>
 #include <map>
+#include <numeric>
 #include <thread>
+#include <tuple>
 
 namespace bk {
 
@@ -80,6 +82,26 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   }
   const int nr = int(T.edge3.size()) - 1;
   T.nr = nr;
+  T.ring_u.assign(nr, 0);
+  for (int r = 1; r <= nr; ++r) {
+    int U = 0;
+    while (9 * int64_t(U + 1) * (U + 1) < T.edge3[r] * T.edge3[r]) ++U;
+    T.ring_u[r - 1] = U;
+  }
+  // grid sizes: 2^a and 3 * 2^a from 16 up (the sizes the FFT stages take), then N_g
+  if (k3.coarse_grids)
+    for (int base : {2, 3})
+      for (int m = base; m < ng; m *= 2)
+        if (m >= 16) T.grid_sizes.push_back(m);
+  std::sort(T.grid_sizes.begin(), T.grid_sizes.end());
+  T.grid_sizes.push_back(ng);
+  auto level_of = [&](int ra, int rb, int rc) {
+    const int ua = T.ring_u[ra - 1], ub = T.ring_u[rb - 1], uc = T.ring_u[rc - 1];
+    const int need = std::max(ua + ub + uc + 1, 2 * std::max(ua, std::max(ub, uc)) + 1);
+    for (size_t L = 0; L < T.grid_sizes.size(); ++L)
+      if (T.grid_sizes[L] >= need) return int32_t(L);
+    return int32_t(T.grid_sizes.size() - 1);  // N_g: exact for every combination
+  };
   const int lim = ng / 3 + 1;
   T.lim = lim;
   const int side_len = 2 * lim + 1;
@@ -208,6 +230,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     int32_t ra, rb, rc;
     int32_t bin;
     int32_t mult;
+    int32_t level;  // x_perp grid
     int64_t ntri;
   };
   std::vector<std::vector<ComboRec>> per_pt(pts.size());
@@ -290,6 +313,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
               cr.rb = rb;
               cr.rc = rc;
               cr.bin = bin;
+              cr.level = level_of(ra, rb, rc);
               cr.ntri = nt;
               const bool self_partner = (a == 0) || (bb == 0 && ra == rc);
               cr.mult = self_partner ? 1 : 2;
@@ -341,136 +365,241 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     for (int i = 0; i < n_bins; ++i)
       T.bin_empty_lm[size_t(j) * n_bins + i] = (T.bin_count[i] == 0 || T.bin_den[size_t(j) * n_bins + i] == 0.0);
 
-  // ---- K3 work items.  Pairs are (slot A ring, slot C ring); the N dimension
-  // is the slot-B ring.  For every pair the kept slot-B rings are cut into
-  // windows of kTileN consecutive rings; windows are packed greedily into
-  // items of up to ppi pairs sharing one window.
-  std::vector<int64_t> combo_item_slot;  // per combination in (pt, enumeration) order
-  combo_item_slot.reserve(total);
-  std::vector<std::vector<int64_t>> pt_combo_slot(pts.size());
+  // ---- K3 work items.  Pairs are (slot A ring, slot C ring); the MFMA N
+  // dimension is the slot-B ring.  Per plane triple, the kept slot-B rings of
+  // every pair are cut into windows of kTileN consecutive rings (segments); a
+  // segment is summed on the largest grid its combinations need.  Segments
+  // are packed into items of up to ppi pairs sharing one window, grid by grid
+  // from the largest down; the free rows of an item are then filled with
+  // segments of smaller grids that fit its window (a larger grid is still
+  // exact).  Items of one grid are finally gathered into workgroups of up to
+  // kItemsPerGroup across neighbouring plane triples while the staged sides
+  // stay within kMaxGroupSides.
+  const int n_levels = int(T.grid_sizes.size());
+  struct Seg {
+    int level, ra, rc, lo, hi;
+    std::vector<int> idx;
+  };
+  struct PItem {
+    int32_t pt;
+    int lo;
+    std::vector<int> segs;
+  };
+  std::vector<std::vector<Seg>> pt_segs(pts.size());
+  std::vector<std::vector<PItem>> level_items(n_levels);
+  double useful = 0.0;
   for (size_t ip = 0; ip < pts.size(); ++ip) {
     auto& recs = per_pt[ip];
     if (recs.empty()) continue;
-    const int a = pts[ip].a, bb = pts[ip].b, c = a + bb;
-    // segments: (ra, rc, window start) -> list of combo indices
-    struct Seg {
-      int ra, rc, lo, hi;
-      std::vector<int> idx;
-    };
-    std::map<std::pair<int, int>, std::vector<int>> by_pair;
+    auto& segs = pt_segs[ip];
+    for (const ComboRec& cr : recs) {
+      const double m = double(T.grid_sizes[cr.level]);
+      useful += m * m;  // on the combination's own grid: the work the method needs
+    }
+    std::map<std::pair<int, int>, std::vector<int>> by_pair;  // (ra, rc) -> combos
     for (int i = 0; i < int(recs.size()); ++i) by_pair[{recs[i].ra, recs[i].rc}].push_back(i);
-    std::vector<Seg> segs;
+    std::vector<double> best;
+    std::vector<int> cut;
     for (auto& kv : by_pair) {
       auto& v = kv.second;
       std::sort(v.begin(), v.end(), [&](int x, int y) { return recs[x].rb < recs[y].rb; });
-      size_t p = 0;
-      while (p < v.size()) {
+      // Cut the pair's slot-B rings into windows spanning < kTileN rings, each
+      // summed on its largest grid, minimising the total sum of m^2 (one row
+      // of kTileN columns per window): best[i] covers the first i rings.
+      const int nv = int(v.size());
+      best.assign(nv + 1, 0.0);
+      cut.assign(nv + 1, 0);
+      for (int i = 1; i <= nv; ++i) {
+        best[i] = 1e300;
+        int lev = 0;
+        for (int j = i - 1; j >= 0 && recs[v[i - 1]].rb - recs[v[j]].rb < kTileN; --j) {
+          lev = std::max(lev, int(recs[v[j]].level));
+          const double m = double(T.grid_sizes[lev]);
+          if (best[j] + m * m < best[i]) {
+            best[i] = best[j] + m * m;
+            cut[i] = j;
+          }
+        }
+      }
+      std::vector<std::pair<int, int>> spans;
+      for (int i = nv; i > 0; i = cut[i]) spans.push_back({cut[i], i});
+      for (auto it = spans.rbegin(); it != spans.rend(); ++it) {
         Seg sg;
         sg.ra = kv.first.first;
         sg.rc = kv.first.second;
-        sg.lo = recs[v[p]].rb;
-        while (p < v.size() && recs[v[p]].rb < sg.lo + kTileN) sg.idx.push_back(v[p++]);
+        sg.lo = recs[v[it->first]].rb;
+        sg.level = 0;
+        for (int q = it->first; q < it->second; ++q) {
+          sg.level = std::max(sg.level, int(recs[v[q]].level));
+          sg.idx.push_back(v[q]);
+        }
         sg.hi = recs[sg.idx.back()].rb;
         segs.push_back(std::move(sg));
       }
     }
-    std::sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
-      return x.lo != y.lo ? x.lo < y.lo : (x.hi != y.hi ? x.hi < y.hi : (x.ra != y.ra ? x.ra < y.ra : x.rc < y.rc));
-    });
-    // greedy packing into items
-    struct Item {
-      int lo;
-      std::vector<int> segs;
-    };
-    std::vector<Item> its;
-    for (int s = 0; s < int(segs.size()); ++s) {
-      if (its.empty() || int(its.back().segs.size()) == ppi || segs[s].hi >= its.back().lo + kTileN)
-        its.push_back({segs[s].lo, {}});
-      its.back().segs.push_back(s);
+    // per level: segments sorted by (lo, hi, ra, rc)
+    std::vector<std::vector<int>> by_level(n_levels);
+    for (int sidx = 0; sidx < int(segs.size()); ++sidx) by_level[segs[sidx].level].push_back(sidx);
+    for (auto& v : by_level)
+      std::sort(v.begin(), v.end(), [&](int x, int y) {
+        const Seg &sx = segs[x], &sy = segs[y];
+        return sx.lo != sy.lo ? sx.lo < sy.lo : (sx.hi != sy.hi ? sx.hi < sy.hi : (sx.ra != sy.ra ? sx.ra < sy.ra : sx.rc < sy.rc));
+      });
+    std::vector<char> used(segs.size(), 0);
+    for (int L = n_levels - 1; L >= 0; --L) {
+      std::vector<PItem> its;
+      for (int sidx : by_level[L]) {
+        if (used[sidx]) continue;
+        const Seg& sg = segs[sidx];
+        if (its.empty() || int(its.back().segs.size()) == ppi || sg.hi >= its.back().lo + kTileN)
+          its.push_back({int32_t(ip), sg.lo, {}});
+        its.back().segs.push_back(sidx);
+        used[sidx] = 1;
+      }
+      for (auto& it : its) {
+        for (int l2 = L - 1; l2 >= 0 && int(it.segs.size()) < ppi; --l2) {
+          const auto& v = by_level[l2];
+          auto first = std::lower_bound(v.begin(), v.end(), it.lo, [&](int x, int lo) { return segs[x].lo < lo; });
+          for (auto q = first; q != v.end() && segs[*q].lo < it.lo + kTileN && int(it.segs.size()) < ppi; ++q) {
+            if (used[*q] || segs[*q].hi >= it.lo + kTileN) continue;
+            it.segs.push_back(*q);
+            used[*q] = 1;
+          }
+        }
+        for (int sidx : it.segs) {
+          segs[sidx].level = L;
+          for (int ci : segs[sidx].idx) recs[ci].level = L;  // the grid the combination is summed on
+        }
+        level_items[L].push_back(std::move(it));
+      }
     }
-    // groups of kItemsPerGroup items; each group stages the sides its items use
-    std::vector<int64_t> slot_of(recs.size(), -1);
-    for (size_t g0 = 0; g0 < its.size(); g0 += kItemsPerGroup) {
-      const size_t g1 = std::min(its.size(), g0 + kItemsPerGroup);
+  }
+  T.useful_terms = useful;
+
+  std::vector<std::vector<int64_t>> pt_combo_slot(pts.size());
+  for (size_t ip = 0; ip < pts.size(); ++ip) pt_combo_slot[ip].assign(per_pt[ip].size(), -1);
+  std::map<std::pair<int32_t, int32_t>, int32_t> gside_tmp;  // (level, side) -> id in first-use order
+  std::vector<std::pair<int32_t, int32_t>> gside_key;
+  auto gside_id = [&](int32_t level, int32_t sidx) {
+    auto it = gside_tmp.find({level, sidx});
+    if (it != gside_tmp.end()) return it->second;
+    const int32_t id = int32_t(gside_key.size());
+    gside_tmp[{level, sidx}] = id;
+    gside_key.push_back({level, sidx});
+    return id;
+  };
+  // sides an item stages, and its slot-B rings kept by some pair (bit j: ring lo + j)
+  auto item_sides = [&](const PItem& it, std::vector<int32_t>* out, uint32_t* b_used) {
+    const int a = pts[it.pt].a, bb = pts[it.pt].b, c = a + bb;
+    const auto& segs = pt_segs[it.pt];
+    const auto& recs = per_pt[it.pt];
+    uint32_t bu = 0;
+    for (int sidx : it.segs) {
+      out->push_back(side(segs[sidx].ra, a));
+      out->push_back(side(segs[sidx].rc, c));
+      for (int ci : segs[sidx].idx) bu |= 1u << (recs[ci].rb - it.lo);
+    }
+    for (int j = 0; j < kTileN; ++j)
+      if (bu >> j & 1u) out->push_back(side(it.lo + j, bb));
+    *b_used = bu;
+  };
+  for (int L = n_levels - 1; L >= 0; --L) {
+    const auto& its = level_items[L];
+    const int m = T.grid_sizes[L];
+    size_t g0 = 0;
+    while (g0 < its.size()) {
+      std::vector<int32_t> gs;  // sorted, unique
+      std::vector<uint32_t> b_used;
+      size_t g1 = g0;
+      while (g1 < its.size() && g1 - g0 < size_t(kItemsPerGroup)) {
+        std::vector<int32_t> add;
+        uint32_t bu = 0;
+        item_sides(its[g1], &add, &bu);
+        std::vector<int32_t> merged(gs);
+        merged.insert(merged.end(), add.begin(), add.end());
+        std::sort(merged.begin(), merged.end());
+        merged.erase(std::unique(merged.begin(), merged.end()), merged.end());
+        if (g1 > g0 && int(merged.size()) > kMaxGroupSides) break;
+        gs.swap(merged);
+        b_used.push_back(bu);
+        ++g1;
+      }
       GroupDesc gd{};
       gd.side_begin = int32_t(T.group_sides.size());
       gd.item_begin = int32_t(T.items.size());
       gd.n_items = int32_t(g1 - g0);
       gd.conj_mask = 4;  // slot C is plane -(a+b); D(r, 0) is real, so conj is harmless on (0,0,0)
+      gd.grid = m;
       // LDS slots: the group's sides numbered in (plane, ring) order, so rows
       // of a tile that read different rings of one plane read different banks.
+      std::sort(gs.begin(), gs.end(), [&](int32_t x, int32_t y) {
+        return T.side_plane[x] != T.side_plane[y] ? T.side_plane[x] < T.side_plane[y] : T.side_ring[x] < T.side_ring[y];
+      });
       std::map<int32_t, int> lds;  // side index -> slot
-      for (size_t ii = g0; ii < g1; ++ii) {
-        const Item& it = its[ii];
-        for (int p = 0; p < int(it.segs.size()); ++p) {
-          lds[side(segs[it.segs[p]].ra, a)] = 0;
-          lds[side(segs[it.segs[p]].rc, c)] = 0;
-        }
-        for (int j = 0; j < kTileN; ++j) {
-          const int32_t sidx = side(it.lo + j, bb);
-          if (sidx >= 0) lds[sidx] = 0;
-        }
+      for (size_t k = 0; k < gs.size(); ++k) {
+        lds[gs[k]] = int(k);
+        T.group_sides.push_back(gside_id(L, gs[k]));
       }
-      {
-        std::vector<int32_t> order;
-        for (auto& kv : lds) order.push_back(kv.first);
-        std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-          return T.side_plane[x] != T.side_plane[y] ? T.side_plane[x] < T.side_plane[y]
-                                                    : T.side_ring[x] < T.side_ring[y];
-        });
-        for (size_t k = 0; k < order.size(); ++k) {
-          lds[order[k]] = int(k);
-          T.group_sides.push_back(order[k]);
-        }
-      }
+      const int zero_slot = int(gs.size());
+      if (zero_slot > 255) return "too many sides in one workgroup";
+      gd.n_sides = zero_slot;
       auto slot = [&](int32_t sidx) -> uint8_t { return uint8_t(lds.at(sidx)); };
-      std::vector<ItemDesc> descs(g1 - g0);
-      std::vector<std::vector<std::pair<int, int>>> pending(g1 - g0);  // (pair row, n-slot) -> fill later
       for (size_t ii = g0; ii < g1; ++ii) {
-        ItemDesc& d = descs[ii - g0];
-        const Item& it = its[ii];
+        const PItem& it = its[ii];
+        const int a = pts[it.pt].a, bb = pts[it.pt].b, c = a + bb;
+        const auto& segs = pt_segs[it.pt];
+        const auto& recs = per_pt[it.pt];
+        ItemDesc d;
         for (int p = 0; p < ppi; ++p) {
           if (p < int(it.segs.size())) {
-            const Seg& sg = segs[it.segs[p]];
-            d.a_slot[p] = slot(side(sg.ra, a));
-            d.c_slot[p] = slot(side(sg.rc, c));
+            d.a_slot[p] = slot(side(segs[it.segs[p]].ra, a));
+            d.c_slot[p] = slot(side(segs[it.segs[p]].rc, c));
+          } else {
+            d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
           }
         }
-        for (int j = 0; j < kTileN; ++j) {
-          const int rbj = it.lo + j;
-          const int32_t sidx = side(rbj, bb);
-          if (sidx >= 0 && !(a == 0 && bb == 0 && rbj == 1)) d.b_slot[j] = slot(sidx);
-        }
-      }
-      const int zero_slot = int(lds.size());
-      gd.n_sides = zero_slot;
-      if (zero_slot > 255) return "too many sides in one workgroup";
-      for (size_t ii = g0; ii < g1; ++ii) {
-        ItemDesc& d = descs[ii - g0];
-        const Item& it = its[ii];
-        for (int p = int(it.segs.size()); p < ppi; ++p) d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
-        for (int j = 0; j < kTileN; ++j) {
-          const int rbj = it.lo + j;
-          const int32_t sidx = side(rbj, bb);
-          if (sidx < 0 || (a == 0 && bb == 0 && rbj == 1)) d.b_slot[j] = uint8_t(zero_slot);
-        }
-        const int64_t item_index = int64_t(T.items.size()) + int64_t(ii - g0);
-        for (int p = 0; p < int(it.segs.size()); ++p) {
-          const Seg& sg = segs[it.segs[p]];
-          for (int ci : sg.idx) slot_of[ci] = item_index * (ppi * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
-        }
-        T.dense_terms += double(ppi) * kTileN;
+        for (int p = ppi; p < kMaxPairsPerItem; ++p) d.a_slot[p] = d.c_slot[p] = uint8_t(zero_slot);
+        const uint32_t bu = b_used[ii - g0];
+        for (int j = 0; j < kTileN; ++j) d.b_slot[j] = (bu >> j & 1u) ? slot(side(it.lo + j, bb)) : uint8_t(zero_slot);
+        const int64_t item_index = int64_t(T.items.size());
+        auto& slot_of = pt_combo_slot[it.pt];
+        for (int p = 0; p < int(it.segs.size()); ++p)
+          for (int ci : segs[it.segs[p]].idx)
+            slot_of[ci] = item_index * (ppi * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
+        T.items.push_back(d);
+        T.dense_terms += double(ppi) * kTileN * double(m) * double(m);
       }
       T.max_group_sides = std::max(T.max_group_sides, zero_slot + 1);
-      for (auto& d : descs) T.items.push_back(d);
       T.groups.push_back(gd);
+      g0 = g1;
     }
-    pt_combo_slot[ip] = std::move(slot_of);
   }
-  T.useful_terms = double(total);
-  const double X = double(ng) * double(ng);
-  T.dense_terms *= X;
-  T.useful_terms *= X;
+  std::vector<std::vector<Seg>>().swap(pt_segs);
+  std::vector<std::vector<PItem>>().swap(level_items);
+
+  // ---- grid sides in (level, side) order and their offsets in D
+  {
+    std::vector<int32_t> order(gside_key.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int32_t(i);
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return gside_key[x] < gside_key[y]; });
+    std::vector<int32_t> remap(order.size());
+    const int n_levels = int(T.grid_sizes.size());
+    T.level_gside_begin.assign(n_levels + 1, 0);
+    int64_t off = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+      const auto& key = gside_key[order[k]];
+      remap[order[k]] = int32_t(k);
+      T.gside_level.push_back(key.first);
+      T.gside_side.push_back(key.second);
+      T.gside_off.push_back(off);
+      const int64_t m = T.grid_sizes[key.first];
+      off += m * m;
+      T.level_gside_begin[key.first + 1] += 1;
+    }
+    for (int L = 0; L < n_levels; ++L) T.level_gside_begin[L + 1] += T.level_gside_begin[L];
+    T.d_elems = off;
+    for (auto& g : T.group_sides) g = remap[g];
+  }
 
   // ---- per-combination coefficients in bin order (counting sort, stable in pt order)
   T.bin_ptr.assign(n_bins + 1, 0);
@@ -485,11 +614,14 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     for (size_t i = 0; i < per_pt[ip].size(); ++i) {
       const ComboRec& cr = per_pt[ip][i];
       const int64_t pos = fill[cr.bin]++;
+      const double mg = double(T.grid_sizes[cr.level]);
+      const double grid_scale = (double(ng) * double(ng)) / (mg * mg);  // S on the m-grid is (m/N_g)^2 S
       T.combo_bin[pos] = cr.bin;
       T.combo_slot[pos] = pt_combo_slot[ip][i];
       for (int j = 0; j < nlm; ++j) {
         const double den = T.bin_den[size_t(j) * n_bins + cr.bin];
-        T.combo_coef[size_t(pos) * nlm + j] = den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den : 0.0;
+        T.combo_coef[size_t(pos) * nlm + j] =
+            den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den * grid_scale : 0.0;
       }
     }
     std::vector<ComboRec>().swap(per_pt[ip]);

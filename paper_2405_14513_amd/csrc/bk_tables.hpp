@@ -13,6 +13,7 @@ namespace bk {
 // Shape of the contraction's work items (chosen per plan).
 struct K3Shape {
   int pairs_per_item = 32;  // 32 (two row tiles per wave) or 64 (four)
+  bool coarse_grids = true;  // evaluate each combination on the smallest alias-free x_perp grid
 };
 
 struct Binning {
@@ -29,16 +30,19 @@ constexpr int kTileN = 16;           // third-slot rings per work item (MFMA N)
 constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 2 or 4 tiles
 constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, all on one plane triple
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
+constexpr int kMaxGroupSides = 120;  // sides a workgroup gathering several items may stage
 
-// One workgroup of the contraction kernel: a canonical plane triple and up to
-// kItemsPerGroup work items that share the sides staged in LDS.
+// One workgroup of the contraction kernel: up to kItemsPerGroup work items on
+// one grid (from one or a few neighbouring plane triples) that share the
+// sides staged in LDS.
 struct GroupDesc {
   int32_t side_begin;  // into group_sides
   int32_t n_sides;     // sides staged (the last LDS slot, n_sides, is all zeros)
   int32_t item_begin;  // first work item
   int32_t n_items;
   int32_t conj_mask;   // bit s set: slot s (0 = A, 1 = B, 2 = C) is a negative plane -> conjugate D
-  int32_t pad[3];
+  int32_t grid;        // x_perp grid size m of every combination in the group (sum over m^2 points)
+  int32_t pad[2];
 };
 
 // One work item: up to kMaxPairsPerItem pairs of (slot A ring, slot C ring)
@@ -80,10 +84,24 @@ struct Tables {
   std::vector<double> bin_mean;          // [n_bins][3]
   std::vector<uint8_t> bin_empty_lm;     // [n_lm][n_bins] 1 if NaN
 
+  // x_perp grids.  A combination of rings whose modes reach |u_x|, |u_y| <= U
+  // is summed exactly on any m x m grid with m > U_A + U_B + U_C (no closure
+  // u_A + u_B + u_C = 0 mod m other than 0 fits) and m > 2 max U (every
+  // side's modes keep distinct positions mod m); it takes the smallest grid
+  // size of the list that qualifies, and its S is rescaled by (N_g / m)^2.
+  std::vector<int32_t> ring_u;           // U per ring (index r-1): largest |u_x| with |u_x| < R_r
+  std::vector<int32_t> grid_sizes;       // ascending; the last is N_g
+  // grid sides: (side, grid level) pairs that some combination uses, in
+  // (level, side) order; D holds m^2 points for each, at gside_off
+  std::vector<int32_t> gside_side, gside_level;
+  std::vector<int64_t> gside_off;        // complex elements from the start of a field's D
+  std::vector<int32_t> level_gside_begin;  // [levels + 1]
+  int64_t d_elems = 0;                   // complex elements of D per field
+
   // K3 decomposition
   std::vector<GroupDesc> groups;
   std::vector<ItemDesc> items;
-  std::vector<int32_t> group_sides;      // side index per LDS slot
+  std::vector<int32_t> group_sides;      // grid-side index per LDS slot
   int max_group_sides = 0;
   double dense_terms = 0.0, useful_terms = 0.0;
 };

@@ -211,6 +211,15 @@ def test_mfma_lane_layout(prec):
             assert P[lane, k] == want, (lane, k, P[lane, k], want)
 
 
+def side_D_on_grid(Delta, geom, ring, plane, m):
+    """Eq. 9 evaluated on an m x m grid: the ring's modes placed at u mod m."""
+    ng = Delta.shape[0]
+    modes = geom.rings.modes[ring - 1]
+    folded = np.zeros((m, m), dtype=np.complex128)
+    np.add.at(folded, (modes[:, 0] % m, modes[:, 1] % m), Delta[modes[:, 0] % ng, modes[:, 1] % ng, plane % ng])
+    return np.fft.fft2(folded)
+
+
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
 def test_stage_buffers_match_oracle(prec):
     """Delta planes (K1) and ring sums D (K2, Eq. 9) against numpy's FFT."""
@@ -237,12 +246,20 @@ def test_stage_buffers_match_oracle(prec):
         tol = 1e-14 if prec == 2 else 2e-6
         assert np.abs(F - ref).max() < tol * np.abs(ref).max()
         D = bk.bk_debug_get_buffer(est.plan, 1, prec)
-        tab = bk.bk_debug_get_buffer(est.plan, 2, prec).reshape(-1, 2)
-        D = D.reshape(len(tab), ng, ng)
-        assert set(map(tuple, tab.tolist())) == {(int(r), int(n)) for r, n in zip(g.sides.ring, g.sides.plane) if n >= 0}
-        for i, (r, n) in enumerate(tab):
-            Dref = side_D(Dl, g, int(r), int(n)) * scale
-            assert np.abs(D[i] - Dref).max() < tol * max(np.abs(Dref).max(), 1e-300), (r, n)
+        tab = bk.bk_debug_get_buffer(est.plan, 2, prec).reshape(-1, 3)
+        assert D.size == int((tab[:, 2].astype(np.int64) ** 2).sum())
+        stored = {(int(r), int(n)) for r, n in zip(g.sides.ring, g.sides.plane) if n >= 0}
+        assert {(int(r), int(n)) for r, n, _ in tab} <= stored
+        assert set(tab[:, 2].tolist()) <= {16, 24, 32, 48}
+        off = 0
+        for r, n, m in tab:
+            Dm = D[off:off + m * m].reshape(m, m)
+            off += m * m
+            if m == ng:
+                Dref = side_D(Dl, g, int(r), int(n)) * scale
+            else:
+                Dref = side_D_on_grid(Dl, g, int(r), int(n), int(m)) * scale
+            assert np.abs(Dm - Dref).max() < tol * max(np.abs(Dref).max(), 1e-300), (r, n, m)
     finally:
         est.close()
 
