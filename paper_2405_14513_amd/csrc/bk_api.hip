@@ -165,18 +165,20 @@ constexpr bool prec_is_f32() {
   return sizeof(T) == 4;
 }
 
-// LDS bytes of the contraction for a chunk of ch points, 0 if the chunk does
-// not divide every grid level's m^2 points or exceeds 64 KiB / the per-thread
-// load budget.
+// LDS bytes of the contraction for a chunk of ch points (two buffers of every
+// staged slot plus the zero slot), 0 if the chunk does not divide every grid
+// level's m^2 points, gives fewer than 8 16-byte units per slot, needs more
+// staging lines than the kernel issues, or exceeds the 160 KiB of a CU.
 size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
   const size_t cs = prec == BK_F32 ? 8 : 16;
+  const int units = int(size_t(ch) * cs / 16);
+  if (units < 8 || units % 8 != 0) return 0;
   for (int m : T.grid_sizes)
     if ((long(m) * m) % ch != 0) return 0;
-  const size_t slot = prec == BK_F32 ? size_t(ch + 1) * cs : size_t(2 * ch + 1) * (cs / 2);
-  const size_t lds = size_t(T.max_group_sides) * slot;
-  const long loads = long(T.max_group_sides - 1) * (ch / int(16 / cs));
-  if (lds > 65536 || loads > long(bk::kK3MaxLoads) * bk::kK3Threads) return 0;
-  return lds;
+  const size_t slot = size_t(ch) * cs;
+  if (size_t(T.max_group_sides - 1) * slot > size_t(bk::kK3MaxLines) * bk::kItemsPerGroup * 1024) return 0;
+  const size_t lds = 2 * size_t(T.max_group_sides) * slot;
+  return lds <= 163840 ? lds : 0;
 }
 
 // LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
@@ -195,6 +197,45 @@ int pick_tb(int n, size_t elem_bytes) {
   while (tb > 1 && (fft_lds_bytes(n, tb, elem_bytes) > 73728 || n % tb != 0)) tb /= 2;
   return tb;
 }
+
+#define BK_K3(TT, CHV, TV)                                                                                       \
+  hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,            \
+                     long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides, p->d_S,           \
+                     p->n_items)
+
+// Contraction launch for the plan's chunk and row tiles (the chunks k3_lds_bytes allows).
+void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
+  const bool t2 = p->tab.k3.pairs_per_item == 32;
+  if (p->k3_chunk == 64 && t2)
+    BK_K3(float, 64, 2);
+  else if (p->k3_chunk == 64)
+    BK_K3(float, 64, 4);
+  else if (p->k3_chunk == 32 && t2)
+    BK_K3(float, 32, 2);
+  else if (p->k3_chunk == 32)
+    BK_K3(float, 32, 4);
+  else if (t2)
+    BK_K3(float, 16, 2);
+  else
+    BK_K3(float, 16, 4);
+}
+
+void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
+  const bool t2 = p->tab.k3.pairs_per_item == 32;
+  if (p->k3_chunk == 32 && t2)
+    BK_K3(double, 32, 2);
+  else if (p->k3_chunk == 32)
+    BK_K3(double, 32, 4);
+  else if (p->k3_chunk == 16 && t2)
+    BK_K3(double, 16, 2);
+  else if (p->k3_chunk == 16)
+    BK_K3(double, 16, 4);
+  else if (t2)
+    BK_K3(double, 8, 2);
+  else
+    BK_K3(double, 8, 4);
+}
+#undef BK_K3
 
 template <typename T>
 bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
@@ -249,24 +290,7 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   // K3: triple products
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
-#define BK_K3(CHV, TV)                                                                                          \
-  hipLaunchKernelGGL((bk::k3_contract_kernel<T, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,            \
-                     long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides, p->d_S,           \
-                     p->n_items)
-    const int tiles = p->tab.k3.pairs_per_item / 16;
-    if (p->k3_chunk == 64 && tiles == 2)
-      BK_K3(64, 2);
-    else if (p->k3_chunk == 64)
-      BK_K3(64, 4);
-    else if (p->k3_chunk == 32 && tiles == 2)
-      BK_K3(32, 2);
-    else if (p->k3_chunk == 32)
-      BK_K3(32, 4);
-    else if (tiles == 2)
-      BK_K3(16, 2);
-    else
-      BK_K3(16, 4);
-#undef BK_K3
+    launch_k3(p, D, g3, st);
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[3], st));
@@ -374,11 +398,11 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   p->device = device;
   p->max_batch = max_batch;
   p->sh = sh;
-  // Work-item shape: float32 is MFMA-issue bound and keeps two row tiles per
-  // wave (less padding); float64 moves twice the LDS bytes per MFMA and runs
-  // faster with four tiles sharing each slot-B read.  BK_K3_PAIRS overrides.
+  // Work-item shape: two row tiles per wave (32 pairs) in both precisions;
+  // four tiles pad more and, in float64, need too many registers for four
+  // waves per SIMD.  BK_K3_PAIRS=64 selects four tiles.
   bk::K3Shape shape;
-  shape.pairs_per_item = prec == BK_F32 ? 32 : 64;
+  shape.pairs_per_item = 32;
   if (const char* v = std::getenv("BK_K3_PAIRS")) shape.pairs_per_item = std::atoi(v);
   if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
@@ -525,20 +549,21 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   std::vector<int64_t>().swap(T.combo_slot);
 
   {
-    // largest chunk whose staging fits 64 KiB of LDS and the per-thread load budget
+    // largest chunk whose two staging buffers fit 64 KiB (two workgroups per
+    // CU), else the smallest valid one
     p->k3_chunk = 0;
-    for (int ch : {64, 32, 16}) {
+    for (int ch : {64, 32, 16, 8}) {
       const size_t lds = k3_lds_bytes(T, prec, ch);
-      if (lds) {
+      if (lds && (lds <= 65536 || p->k3_chunk == 0)) {
         p->k3_chunk = ch;
         p->lds_k3 = lds;
-        break;
+        if (lds <= 65536) break;
       }
     }
     if (p->k3_chunk == 0) {
       release(p);
       delete p;
-      return fail(BK_ERR_ARG, "workgroup staging exceeds 64 KiB of LDS or the per-thread load budget");
+      return fail(BK_ERR_ARG, "workgroup staging does not fit the LDS");
     }
   }
   {
@@ -926,7 +951,7 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
       c_fft.push_back(tb);
       c_k2.push_back(tb);
     }
-  for (int ch : {16, 32, 64})
+  for (int ch : {8, 16, 32, 64})
     if (k3_lds_bytes(p->tab, p->prec, ch)) c_k3.push_back(ch);
   if (c_fft.empty() || c_k3.empty()) return fail(BK_ERR_ARG, "no valid tile choice to tune");
   const int saved[3] = {p->fft_tb, p->k2_tb, p->k3_chunk};

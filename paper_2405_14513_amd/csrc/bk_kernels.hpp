@@ -208,35 +208,48 @@ struct Mfma<double> {
   static __device__ __forceinline__ int out_row(int kq, int k) { return 4 * k + kq; }
 };
 
-// LDS slot stride in complex elements: an odd number of 8-byte words between
-// slots so the 16 rows of an MFMA tile, reading 16 different slots at one
-// point, fall in different banks.
-//
-// float32: slot = CH interleaved complex values (8-byte reads), stride CH + 1.
-// float64: slot = CH real parts then CH imaginary parts (two 8-byte reads per
-// value instead of one 16-byte read), stride 2 CH + 1 doubles.
+// LDS staging of the contraction.  A slot holds CH consecutive x_perp points
+// of one side's D as 16-byte units (2 float32 or 1 float64 complex points),
+// slot after slot with no padding, so whole 1 KiB lines are filled by direct
+// global-to-LDS loads (64 lanes x 16 bytes, lane i to byte 16 i).  Unit u of
+// slot s is stored at position u ^ (s & 7): the 8 rows of an MFMA tile that
+// one 16-byte LDS read serves together fall in different banks whenever their
+// slots differ mod 8.
 template <typename T, int CH>
-struct K3Lds {
-  static constexpr bool split = sizeof(T) == 8;
-  static constexpr int stride = split ? 2 * CH + 1 : CH + 1;     // in units of T (split) or complex
-  static constexpr int vec = 16 / int(sizeof(cplx<T>));          // complex per 16-byte global load
-  static constexpr int per_side = CH / vec;                      // 16-byte loads per side per chunk
-  static constexpr size_t slot_bytes = split ? size_t(stride) * sizeof(T) : size_t(stride) * sizeof(cplx<T>);
+struct K3Stage {
+  static constexpr int cs = int(sizeof(cplx<T>));
+  static constexpr int ppu = 16 / cs;           // points per 16-byte unit
+  static constexpr int units = CH / ppu;        // units per slot
+  static constexpr int slot_bytes = CH * cs;
+  static constexpr int steps = units / 4;       // 16-byte reads per operand per chunk
+  static constexpr bool valid = units >= 8 && units % 8 == 0;  // the swizzle needs 8 units per slot
 };
 constexpr int kK3Threads = 64 * kItemsPerGroup;
-constexpr int kK3MaxLoads = 8;  // 16-byte global loads per thread per chunk
+constexpr int kK3MaxLines = 8;  // 1 KiB staging lines per wave per chunk
 
-// One block = one GroupDesc (all on one canonical plane triple and one grid
-// of m x m points), one wave per work item of 16 * TILES ring pairs x 16
-// slot-B rings.  Every CH points of x_perp the block stages the group's sides into LDS (16-byte loads, the next
-// chunk prefetched into registers while the current one is consumed); each
-// wave then forms the pair products P = D_A conj(D_C) (4 points per lane
-// group) and feeds Re P, -Im P against Re D_B, Im D_B into 16x16x4 MFMAs
-// (K = 4 points), one accumulator per row tile.  The chunk's partial sums are
-// added to float64 registers.  Groups come largest grid first and, within a
-// grid, in plane-triple order: the dispatcher deals consecutive blocks to the
-// eight XCDs in turn, so every XCD gets an even share of each grid size, and
-// groups that read the same sides run at about the same time.
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Unit;
+template <>
+struct Unit<float> {
+  typedef f32x4 type;  // two complex points
+};
+template <>
+struct Unit<double> {
+  typedef f64x2v type;  // one complex point
+};
+
+// One block = one GroupDesc (items on one grid of m x m points that share
+// the sides staged in LDS), one wave per work item of 16 * TILES ring pairs
+// x 16 slot-B rings.  The m^2 points are visited in chunks of CH: while the
+// waves contract chunk c from one LDS buffer, the direct loads of chunk c+1
+// fill the other.  Per 16-byte unit step, lane (row, kq) reads unit 4 q + kq
+// of its pair's A and C slots and of its column's B slot, forms the pair
+// products P = D_A conj(D_C) and feeds Re P, -Im P against Re D_B, Im D_B into
+// 16x16x4 MFMAs (K = the 4 points of the lanes' kq), one accumulator per row
+// tile; float32 units carry two points, i.e. two k-steps.  Each chunk's
+// partial sums are added to float64 registers.
 template <typename T, int CH, int TILES>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
@@ -244,59 +257,77 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
                                                                  const ItemDesc* __restrict__ items,
                                                                  const int32_t* __restrict__ group_sides,
                                                                  double* __restrict__ S_out, long n_items_total) {
-  using L = K3Lds<T, CH>;
+  using G = K3Stage<T, CH>;
+  static_assert(G::valid, "the swizzle needs a multiple of 8 units per slot");
+  typedef typename Unit<T>::type unit_t;
   constexpr int kOut = 16 * TILES * kTileN;
-  typedef uint4 v16;
-  extern __shared__ char smem_raw[];
-  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  T* ldsr = reinterpret_cast<T*>(smem_raw);  // split layout view
+  extern __shared__ char smem_raw[];  // starts at LDS address 0 (no static LDS): 16-byte aligned
   const GroupDesc gd = groups[blockIdx.x];
   const int b = blockIdx.y;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int row = lane & 15;
   const int kq = lane >> 4;
-  const cplx<T>* Db = D + size_t(b) * d_elems;
-  const long X = long(gd.grid) * gd.grid;  // the group's grid points (a multiple of CH)
+  const char* Db = reinterpret_cast<const char*>(D + size_t(b) * d_elems);
+  const int nchunks = int((long(gd.grid) * gd.grid) / CH);  // m^2 is a multiple of CH
+  const int buf_bytes = (gd.n_sides + 1) * G::slot_bytes;
+  const int data_bytes = gd.n_sides * G::slot_bytes;
 
-  // zero slot
-  if constexpr (L::split) {
-    for (int i = threadIdx.x; i < L::stride; i += blockDim.x) ldsr[gd.n_sides * L::stride + i] = T(0);
-  } else {
-    for (int i = threadIdx.x; i < L::stride; i += blockDim.x) lds[gd.n_sides * L::stride + i] = {T(0), T(0)};
+  // the zero slot (last) of both buffers
+  for (int i = threadIdx.x; i < G::slot_bytes / 16; i += kK3Threads) {
+    reinterpret_cast<uint4*>(smem_raw + data_bytes)[i] = make_uint4(0u, 0u, 0u, 0u);
+    reinterpret_cast<uint4*>(smem_raw + buf_bytes + data_bytes)[i] = make_uint4(0u, 0u, 0u, 0u);
   }
 
-  // this thread's staging loads: global source and LDS destination per chunk
-  const v16* src[kK3MaxLoads];
-  int dst[kK3MaxLoads];
-  const int n_loads = gd.n_sides * L::per_side;
+  // this wave's staging lines (wave, wave + 8, ...): per lane, the global
+  // source of the 16 bytes it moves; null for lanes past the last slot
+  const int n_lines = (data_bytes + 1023) >> 10;
+  const char* src[kK3MaxLines];
 #pragma unroll
-  for (int i = 0; i < kK3MaxLoads; ++i) {
-    const int q = threadIdx.x + i * kK3Threads;
-    const int qq = q < n_loads ? q : 0;
-    const int sl = qq / L::per_side, v = qq - sl * L::per_side;
-    src[i] = reinterpret_cast<const v16*>(Db + gside_off[group_sides[gd.side_begin + sl]] + v * L::vec);
-    dst[i] = sl * L::stride + v * L::vec;
+  for (int i = 0; i < kK3MaxLines; ++i) {
+    const int o = (wave + 8 * i) * 1024 + lane * 16;
+    src[i] = nullptr;
+    if (o < data_bytes) {
+      const int sl = o / G::slot_bytes;
+      const int u = ((o - sl * G::slot_bytes) >> 4) ^ (sl & 7);
+      src[i] = Db + (gside_off[group_sides[gd.side_begin + sl]] * G::cs + u * 16);
+    }
   }
-  v16 stage[kK3MaxLoads];
+  auto issue = [&](int chunk, int sel) {
+    char* dst = smem_raw + sel * buf_bytes;
 #pragma unroll
-  for (int i = 0; i < kK3MaxLoads; ++i)
-    if (threadIdx.x + i * kK3Threads < n_loads) stage[i] = src[i][0];
+    for (int i = 0; i < kK3MaxLines; ++i) {
+      const int line = wave + 8 * i;
+      if (line < n_lines && src[i])
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(src[i] + long(chunk) * G::slot_bytes),
+                                         reinterpret_cast<uint4*>(dst + line * 1024), 16, 0, 0);
+    }
+  };
+  issue(0, 0);
 
   // Slot C always lies on plane -(a+b) <= 0 and is read as conj D(r, a+b); on
   // the (0,0,0) triple D(r, 0) is real, so the conjugate changes nothing.
   const bool active = wave < gd.n_items;
-  int sa[TILES], sc[TILES], sb = 0;
+  // per operand: byte offsets of the even-step and odd-step reads (the swizzle
+  // flips bit 2 of the unit index when slot & 4, i.e. swaps steps q and q ^ 1)
+  int ae[TILES], ao[TILES], ce[TILES], co[TILES], be = 0, bo = 0;
+  auto offsets = [&](int slot, int& ev, int& od) {
+    const int key = slot & 7;
+    const int base = slot * G::slot_bytes + 16 * (kq ^ (key & 3));
+    const int d = (key & 4) ? 64 : 0;
+    ev = base + d;
+    od = base - d;
+  };
 #pragma unroll
-  for (int t = 0; t < TILES; ++t) sa[t] = sc[t] = 0;
+  for (int t = 0; t < TILES; ++t) ae[t] = ao[t] = ce[t] = co[t] = 0;
   if (active) {
     const ItemDesc& it = items[gd.item_begin + wave];
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
-      sa[t] = it.a_slot[16 * t + row] * L::stride;
-      sc[t] = it.c_slot[16 * t + row] * L::stride;
+      offsets(it.a_slot[16 * t + row], ae[t], ao[t]);
+      offsets(it.c_slot[16 * t + row], ce[t], co[t]);
     }
-    sb = it.b_slot[row] * L::stride;
+    offsets(it.b_slot[row], be, bo);
   }
 
   typedef typename Mfma<T>::acc_t acc_t;
@@ -305,75 +336,55 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   for (int t = 0; t < TILES; ++t)
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[t][k] = 0.0;
-  const long step = long(CH) / L::vec;  // 16-byte units per chunk
-  for (long x0 = 0; x0 < X; x0 += CH) {
-    __syncthreads();  // previous chunk fully consumed
-#pragma unroll
-    for (int i = 0; i < kK3MaxLoads; ++i) {
-      if (threadIdx.x + i * kK3Threads < n_loads) {
-        // slots are 8-byte aligned only (odd stride): store 8 bytes at a time
-        const cplx<T>* v = reinterpret_cast<const cplx<T>*>(&stage[i]);
-        if constexpr (L::split) {
-          ldsr[dst[i]] = v[0].x;
-          ldsr[dst[i] + CH] = v[0].y;
-        } else {
-#pragma unroll
-          for (int e = 0; e < L::vec; ++e) lds[dst[i] + e] = v[e];
-        }
-      }
-    }
+
+  for (int c = 0; c < nchunks; ++c) {
+    // chunk c has landed (each wave waits for its own loads, the barrier for
+    // everyone's) and every wave is done with the buffer chunk c + 1 will fill
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (x0 + CH < X) {
-#pragma unroll
-      for (int i = 0; i < kK3MaxLoads; ++i) {
-        if (threadIdx.x + i * kK3Threads < n_loads) {
-          src[i] += step;
-          stage[i] = src[i][0];
-        }
-      }
-    }
+    if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
     if (active) {
-      // Software pipeline over the CH/4 k-steps: the LDS operands of step
-      // ks+1 are read before the MFMAs of step ks are issued, and the pair
-      // products of a step are formed into their own registers.
+      const char* buf = smem_raw + (c & 1) * buf_bytes;
       acc_t acc[TILES];
 #pragma unroll
       for (int t = 0; t < TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
-      cplx<T> a_n[TILES], c_n[TILES], b_n;
-      auto load_step = [&](int ks, cplx<T>* a, cplx<T>* c, cplx<T>& bvv) {
-        const int xi = ks * 4 + kq;
-        if constexpr (L::split) {
-          bvv = {ldsr[sb + xi], ldsr[sb + CH + xi]};
+      unit_t a_n[TILES], c_n[TILES], b_n;
+      auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t& bv) {
+        const int shift = 64 * q;
+        bv = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? bo : be) + shift);
 #pragma unroll
-          for (int t = 0; t < TILES; ++t) {
-            a[t] = {ldsr[sa[t] + xi], ldsr[sa[t] + CH + xi]};
-            c[t] = {ldsr[sc[t] + xi], ldsr[sc[t] + CH + xi]};
-          }
-        } else {
-          bvv = lds[sb + xi];
-#pragma unroll
-          for (int t = 0; t < TILES; ++t) {
-            a[t] = lds[sa[t] + xi];
-            c[t] = lds[sc[t] + xi];
-          }
+        for (int t = 0; t < TILES; ++t) {
+          a[t] = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? ao[t] : ae[t]) + shift);
+          cc[t] = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? co[t] : ce[t]) + shift);
         }
       };
       load_step(0, a_n, c_n, b_n);
 #pragma unroll
-      for (int ks = 0; ks < CH / 4; ++ks) {
-        // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
-        T pr[TILES], pn[TILES];
+      for (int q = 0; q < G::steps; ++q) {
+        unit_t a_c[TILES], c_c[TILES], b_c = b_n;
 #pragma unroll
         for (int t = 0; t < TILES; ++t) {
-          pr[t] = a_n[t].x * c_n[t].x + a_n[t].y * c_n[t].y;
-          pn[t] = a_n[t].x * c_n[t].y - a_n[t].y * c_n[t].x;
+          a_c[t] = a_n[t];
+          c_c[t] = c_n[t];
         }
-        const T br = b_n.x, bi = b_n.y;
-        if (ks + 1 < CH / 4) load_step(ks + 1, a_n, c_n, b_n);
+        if (q + 1 < G::steps) load_step(q + 1, a_n, c_n, b_n);
 #pragma unroll
-        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], br, acc[t]);
+        for (int h = 0; h < G::ppu; ++h) {
+          // P = D_A conj(D_C); Re(P D_B) = Re P Re D_B + (-Im P) Im D_B
+          T pr[TILES], pn[TILES];
 #pragma unroll
-        for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bi, acc[t]);
+          for (int t = 0; t < TILES; ++t) {
+            const T ar = a_c[t][2 * h], ai = a_c[t][2 * h + 1];
+            const T cr = c_c[t][2 * h], ci = c_c[t][2 * h + 1];
+            pr[t] = ar * cr + ai * ci;
+            pn[t] = ar * ci - ai * cr;
+          }
+          const T br = b_c[2 * h], bi = b_c[2 * h + 1];
+#pragma unroll
+          for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], br, acc[t]);
+#pragma unroll
+          for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bi, acc[t]);
+        }
       }
 #pragma unroll
       for (int t = 0; t < TILES; ++t)
