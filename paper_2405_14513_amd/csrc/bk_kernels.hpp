@@ -212,9 +212,9 @@ struct Mfma<double> {
 // of one side's D as 16-byte units (2 float32 or 1 float64 complex points),
 // slot after slot with no padding, so whole 1 KiB lines are filled by direct
 // global-to-LDS loads (64 lanes x 16 bytes, lane i to byte 16 i).  Unit u of
-// slot s is stored at position u ^ (s & 7): the 8 rows of an MFMA tile that
-// one 16-byte LDS read serves together fall in different banks whenever their
-// slots differ mod 8.
+// slot s is stored at position u ^ key(s), with a 3-bit key per slot chosen on
+// the host: the 8 rows of an MFMA tile that one 16-byte LDS read serves
+// together fall in different banks whenever their slots' keys differ.
 template <typename T, int CH>
 struct K3Stage {
   static constexpr int cs = int(sizeof(cplx<T>));
@@ -289,8 +289,9 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     src[i] = nullptr;
     if (o < data_bytes) {
       const int sl = o / G::slot_bytes;
-      const int u = ((o - sl * G::slot_bytes) >> 4) ^ (sl & 7);
-      src[i] = Db + (gside_off[group_sides[gd.side_begin + sl]] * G::cs + u * 16);
+      const int32_t e = group_sides[gd.side_begin + sl];
+      const int u = ((o - sl * G::slot_bytes) >> 4) ^ (e >> kKeyShift);
+      src[i] = Db + (gside_off[e & ((1 << kKeyShift) - 1)] * G::cs + u * 16);
     }
   }
   auto issue = [&](int chunk, int sel) {
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   // flips bit 2 of the unit index when slot & 4, i.e. swaps steps q and q ^ 1)
   int ae[TILES], ao[TILES], ce[TILES], co[TILES], be = 0, bo = 0;
   auto offsets = [&](int slot, int& ev, int& od) {
-    const int key = slot & 7;
+    const int key = slot < gd.n_sides ? group_sides[gd.side_begin + slot] >> kKeyShift : gd.zero_key;
     const int base = slot * G::slot_bytes + 16 * (kq ^ (key & 3));
     const int d = (key & 4) ? 64 : 0;
     ev = base + d;

@@ -569,6 +569,61 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         T.items.push_back(d);
         T.dense_terms += double(ppi) * kTileN * double(m) * double(m);
       }
+      // LDS swizzle keys: unit u of slot s sits at u ^ key(s), and one 16-byte
+      // read serves 8 rows (or columns) together, so slots read in the same
+      // 8-row phase should carry different keys.  Greedy colouring of the
+      // slots (zero slot included) by how often two of them share a phase.
+      {
+        const int nv = zero_slot + 1;
+        std::vector<int32_t> w(size_t(nv) * nv, 0);
+        int phase[8];
+        auto add_phase = [&](int n) {
+          std::sort(phase, phase + n);
+          n = int(std::unique(phase, phase + n) - phase);
+          for (int x = 0; x < n; ++x)
+            for (int y = 0; y < n; ++y)
+              if (x != y) w[size_t(phase[x]) * nv + phase[y]] += 1;
+        };
+        for (int64_t ii = T.items.size() - (g1 - g0); ii < int64_t(T.items.size()); ++ii) {
+          const ItemDesc& d = T.items[ii];
+          for (int h = 0; h < ppi / 8; ++h) {
+            for (int r = 0; r < 8; ++r) phase[r] = d.a_slot[8 * h + r];
+            add_phase(8);
+            for (int r = 0; r < 8; ++r) phase[r] = d.c_slot[8 * h + r];
+            add_phase(8);
+          }
+          for (int h = 0; h < kTileN / 8; ++h) {
+            for (int r = 0; r < 8; ++r) phase[r] = d.b_slot[8 * h + r];
+            add_phase(8);
+          }
+        }
+        std::vector<int64_t> deg(nv, 0);
+        for (int x = 0; x < nv; ++x)
+          for (int y = 0; y < nv; ++y) deg[x] += w[size_t(x) * nv + y];
+        std::vector<int> order(nv);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] > deg[y]; });
+        std::vector<int> key(nv, -1);
+        auto best_key = [&](int x) {
+          int64_t best = -1;
+          int bk = 0;
+          for (int k = 0; k < 8; ++k) {
+            int64_t c = 0;
+            for (int y = 0; y < nv; ++y)
+              if (y != x && key[y] == k) c += w[size_t(x) * nv + y];
+            if (best < 0 || c < best) {
+              best = c;
+              bk = k;
+            }
+          }
+          return bk;
+        };
+        for (int x : order) key[x] = best_key(x);
+        for (int sweep = 0; sweep < 3; ++sweep)
+          for (int x : order) key[x] = best_key(x);
+        for (int k = 0; k < zero_slot; ++k) T.group_sides[gd.side_begin + k] |= key[k] << kKeyShift;
+        gd.zero_key = key[zero_slot];
+      }
       T.max_group_sides = std::max(T.max_group_sides, zero_slot + 1);
       T.groups.push_back(gd);
       g0 = g1;
@@ -598,7 +653,9 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     }
     for (int L = 0; L < n_levels; ++L) T.level_gside_begin[L + 1] += T.level_gside_begin[L];
     T.d_elems = off;
-    for (auto& g : T.group_sides) g = remap[g];
+    if (order.size() >= (size_t(1) << kKeyShift)) return "too many grid sides";
+    const int32_t low = (int32_t(1) << kKeyShift) - 1;
+    for (auto& g : T.group_sides) g = remap[g & low] | (g & ~low);
   }
 
   // ---- per-combination coefficients in bin order (counting sort, stable in pt order)

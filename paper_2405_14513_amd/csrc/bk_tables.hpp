@@ -30,7 +30,8 @@ constexpr int kTileN = 16;           // third-slot rings per work item (MFMA N)
 constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 2 or 4 tiles
 constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, all on one plane triple
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
-constexpr int kMaxGroupSides = 120;  // sides a workgroup gathering several items may stage
+constexpr int kMaxGroupSides = 120;
+constexpr int kKeyShift = 24;       // group_sides entries: grid side in the low 24 bits, 3-bit key above  // sides a workgroup gathering several items may stage
 
 // One workgroup of the contraction kernel: up to kItemsPerGroup work items on
 // one grid (from one or a few neighbouring plane triples) that share the
@@ -42,7 +43,8 @@ struct GroupDesc {
   int32_t n_items;
   int32_t conj_mask;   // bit s set: slot s (0 = A, 1 = B, 2 = C) is a negative plane -> conjugate D
   int32_t grid;        // x_perp grid size m of every combination in the group (sum over m^2 points)
-  int32_t pad[2];
+  int32_t zero_key;    // LDS swizzle key of the zero slot
+  int32_t pad;
 };
 
 // One work item: up to kMaxPairsPerItem pairs of (slot A ring, slot C ring)
@@ -101,7 +103,7 @@ struct Tables {
   // K3 decomposition
   std::vector<GroupDesc> groups;
   std::vector<ItemDesc> items;
-  std::vector<int32_t> group_sides;      // grid-side index per LDS slot
+  std::vector<int32_t> group_sides;      // per LDS slot: grid-side index | swizzle key << kKeyShift
   int max_group_sides = 0;
   double dense_terms = 0.0, useful_terms = 0.0;
 };
