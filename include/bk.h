@@ -15,7 +15,7 @@
  * modes of the three rings reach |u_x|, |u_y| <= U_1, U_2, U_3, so on an
  * m x m grid with m > U_1 + U_2 + U_3 the only closure mod m is the exact one,
  * and S on that grid is (m / N_g)^2 times S on the N_g grid.  Each
- * combination is summed on the smallest such grid of size 2^a or 3 * 2^a
+ * combination is summed on the smallest such grid of size 2^a, 3 * 2^a or 5 * 2^a
  * (>= 16, and > 2 max U so D needs no wrapped modes), with D evaluated on
  * that grid: the same result, up to rounding, at a fraction of the points.
  *

@@ -36,11 +36,13 @@ bk_status fail(bk_status st, const std::string& msg) {
                   std::string(#call) + ": " + hipGetErrorString(e_));                                    \
   } while (0)
 
+// Radices of an LDS FFT of length n = 2^a 3^b 5^c (a >= 1, b, c <= 1).
 bool fft_shape(int n, bk::FftShape* sh) {
   sh->n = n;
   sh->nstages = 0;
   int m = n;
   if (m % 3 == 0) m /= 3;
+  if (m % 5 == 0) m /= 5;
   if (m < 2 || (m & (m - 1)) != 0) return false;
   while (m % 4 == 0) {
     sh->radix[sh->nstages++] = 4;
@@ -48,6 +50,7 @@ bool fft_shape(int n, bk::FftShape* sh) {
   }
   if (m == 2) sh->radix[sh->nstages++] = 2;
   if (n % 3 == 0) sh->radix[sh->nstages++] = 3;
+  if (n % 5 == 0) sh->radix[sh->nstages++] = 5;
   return true;
 }
 
@@ -328,7 +331,7 @@ extern "C" const char* bk_last_error(void) { return g_last_error.c_str(); }
 namespace {
 
 bk_status check_binning(const bk_binning* bn, bk::FftShape* sh, bk::Binning* b) {
-  if (bn->ng < 8 || bn->ng > 512 || bn->ng % 8 != 0 || !fft_shape(bn->ng, sh))
+  if (bn->ng < 8 || bn->ng > 512 || bn->ng % 8 != 0 || bn->ng % 5 == 0 || !fft_shape(bn->ng, sh))
     return fail(BK_ERR_ARG, "ng must be 2^a or 3*2^a, a multiple of 8, with 8 <= ng <= 512");
   if (bn->n_k1 < 1 || bn->n_mu < 1 || bn->n_t < 1) return fail(BK_ERR_ARG, "bin counts must be >= 1");
   if (!(bn->k1_min >= 0.0) || !(bn->k1_max > bn->k1_min)) return fail(BK_ERR_ARG, "need 0 <= k1_min < k1_max");

@@ -2,9 +2,10 @@
 //
 // All transforms here are forward DFTs, y[k] = sum_j x[j] e^{-2 pi i j k / N}:
 // the 3-D transform of the field (Sec. II) and the ring sums of Eq. 9, whose
-// exponent carries the same minus sign.  N = 2^a 3^b with b <= 1; stages use
-// radix 4, then one radix 2 if a is odd, then one radix 3.  Twiddles are a
-// table exp(-2 pi i t / N), t < N, computed on the host in float64 and cast.
+// exponent carries the same minus sign.  N = 2^a 3^b 5^c with b, c <= 1;
+// stages use radix 4, then one radix 2 if a is odd, then one radix 3 and one
+// radix 5.  Twiddles are a table exp(-2 pi i t / N), t < N, computed on the
+// host in float64 and cast.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,6 +70,21 @@ __device__ __forceinline__ void stockham_pass(const cplx<T>* __restrict__ src, c
       v[0] = cadd(v[0], t1);
       v[1] = cadd(t2, t3);
       v[2] = csub(t2, t3);
+    } else if constexpr (R == 5) {
+      // y_k = sum_j v_j w^{jk}, w = e^{-2 pi i / 5}: pair j with 5 - j
+      const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+      const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+      const cplx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+      const cplx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+      const cplx<T> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+      const cplx<T> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+      const cplx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+      const cplx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+      v[0] = cadd(v[0], cadd(t1, t2));
+      v[1] = {a1.x + b1.y, a1.y - b1.x};  // a1 - i b1
+      v[4] = {a1.x - b1.y, a1.y + b1.x};  // a1 + i b1
+      v[2] = {a2.x + b2.y, a2.y - b2.x};
+      v[3] = {a2.x - b2.y, a2.y + b2.x};
     } else if constexpr (R == 4) {
       const cplx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
       const cplx<T> b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
@@ -96,8 +112,10 @@ __device__ cplx<T>* lds_fft(cplx<T>* b0, cplx<T>* b1, const cplx<T>* tw, const F
       stockham_pass<T, 4>(src, dst, tw, sh.n, ns, lines, ls);
     else if (R == 2)
       stockham_pass<T, 2>(src, dst, tw, sh.n, ns, lines, ls);
-    else
+    else if (R == 3)
       stockham_pass<T, 3>(src, dst, tw, sh.n, ns, lines, ls);
+    else
+      stockham_pass<T, 5>(src, dst, tw, sh.n, ns, lines, ls);
     __syncthreads();
     ns *= R;
     cplx<T>* t = src;

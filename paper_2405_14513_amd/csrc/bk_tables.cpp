@@ -88,11 +88,12 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     while (9 * int64_t(U + 1) * (U + 1) < T.edge3[r] * T.edge3[r]) ++U;
     T.ring_u[r - 1] = U;
   }
-  // grid sizes: 2^a and 3 * 2^a from 16 up (the sizes the FFT stages take), then N_g
+  // grid sizes: 2^a, 3 * 2^a and 5 * 2^a from 16 up, multiples of 8 (the sizes
+  // the FFT stages take), then N_g
   if (k3.coarse_grids)
-    for (int base : {2, 3})
+    for (int base : {2, 3, 5})
       for (int m = base; m < ng; m *= 2)
-        if (m >= 16) T.grid_sizes.push_back(m);
+        if (m >= 16 && m % 8 == 0) T.grid_sizes.push_back(m);
   std::sort(T.grid_sizes.begin(), T.grid_sizes.end());
   T.grid_sizes.push_back(ng);
   auto level_of = [&](int ra, int rb, int rc) {

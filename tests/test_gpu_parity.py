@@ -250,7 +250,7 @@ def test_stage_buffers_match_oracle(prec):
         assert D.size == int((tab[:, 2].astype(np.int64) ** 2).sum())
         stored = {(int(r), int(n)) for r, n in zip(g.sides.ring, g.sides.plane) if n >= 0}
         assert {(int(r), int(n)) for r, n, _ in tab} <= stored
-        assert set(tab[:, 2].tolist()) <= {16, 24, 32, 48}
+        assert set(tab[:, 2].tolist()) <= {16, 24, 32, 40, 48} and 40 in set(tab[:, 2].tolist())  # radix-5 level
         off = 0
         for r, n, m in tab:
             Dm = D[off:off + m * m].reshape(m, m)
