@@ -306,3 +306,47 @@ def test_autotuned_plan_matches_oracle(prec):
         finally:
             fresh.close()
     assert e.value.status == bk.BK_ERR_STATE
+
+
+EDGE_CASES = [
+    # smallest grid: two rings beyond the zero ring, k1 up to N_g/3
+    ("ng8", dict(ng=8, n_k1=2, k1_min=1.0, k1_max=8 / 3, n_mu=3, n_t=2), FieldRecipe(8, seed=21)),
+    # l_max = 12 (49 outputs: the 64-lane binning path)
+    ("lmax12", dict(ng=24, n_k1=2, k1_min=3.0, k1_max=8.0, n_mu=3, n_t=3, l_max=12, m_max=12),
+     FieldRecipe(24, n_s=-1.5, f_ng=0.5, beta=1.0, seed=22)),
+    # m_max < l_max (13 outputs)
+    ("mmax2", dict(ng=24, n_k1=2, k1_min=3.0, k1_max=8.0, n_mu=3, n_t=3, l_max=8, m_max=2),
+     FieldRecipe(24, n_s=-2.0, f_ng=0.5, beta=0.5, seed=23)),
+    # fine (mu, t) bins at a small grid: many empty bins (NaN pattern)
+    ("empty", dict(ng=16, n_k1=3, k1_min=2.5, k1_max=5.0, n_mu=9, n_t=9),
+     FieldRecipe(16, n_s=-2.0, f_ng=0.5, beta=0.5, seed=24)),
+]
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(EDGE_CASES)), ids=[c[0] for c in EDGE_CASES])
+def test_edge_case_parity(case, prec):
+    """Degenerate and boundary configurations against the oracle."""
+    torch = _torch()
+    from paper_2405_14513_amd import bk
+
+    name, kw, recipe = EDGE_CASES[case]
+    _say(f"edge case {name} prec={prec}")
+    b = Binning(kw["ng"], kw["n_k1"], kw["k1_min"], kw["k1_max"], kw["n_mu"], kw["n_t"],
+                l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6))
+    delta = make_field(recipe)
+    ref = estimate(delta, b)
+    est = bk.Estimator(bk.make_binning(kw["ng"], kw["n_k1"], kw["k1_min"], kw["k1_max"], kw["n_mu"], kw["n_t"],
+                                       l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6)), prec=prec)
+    try:
+        s = torch.cuda.current_stream().cuda_stream
+        est.load(torch.from_numpy(delta).cuda(), s)
+        est.estimate(s)
+        assert est.lm_list() == b.lms()
+        assert np.array_equal(est.counts(), ref.counts)
+        err = per_multipole_error(est.multipoles()[0], ref.B)
+        assert err.max() < TOL[prec], err
+        if name == "empty":
+            assert np.isnan(ref.B).any() and (~np.isnan(ref.B)).any()
+    finally:
+        est.close()
