@@ -168,6 +168,36 @@ bk_status bk_group_destroy(bk_group group);
  * to inspect a binning before committing device memory. */
 bk_status bk_count_triangles(const bk_binning* binning, int64_t* out, size_t cap, int64_t* n_combinations);
 
+/* The paper's model field, for its analytic predictions: power spectrum
+ * P(k) = amp k^n_s (k in units of k_f = 2 pi / L, the same units as the
+ * field's DFT normalisation), real-space bispectrum to first order in f_NG
+ * (Eq. 15) B_r = 2 f_NG (P1 P2 + P2 P3 + P3 P1), linear redshift-space
+ * distortion (Eq. 17) B_s = B_r prod_i (1 + beta mu_i^2). */
+typedef struct {
+  double amp;
+  double n_s;
+  double f_ng;
+  double beta;
+} bk_model;
+
+/* Host-only: the discrete prediction [B_l^m]_d (Sec. III.C) for a binning:
+ * B_s at every kept combination's mean-value sides (mu_i = n_i / k_i), binned
+ * with exactly the estimator's weights and N_tri (Eq. 13).  Same layout and
+ * units as bk_get_multipoles for one field, float64
+ * [n_lm][n_k1][n_mu][n_t], NaN where the estimator's bin is empty.  Builds the
+ * plan geometry on the host (no device needed).  Errors: BK_ERR_ARG for an
+ * invalid binning or non-finite model, BK_ERR_SIZE if cap is too small. */
+bk_status bk_discrete_prediction(const bk_binning* binning, const bk_model* model, double* out, size_t cap);
+
+/* Host-only: the continuum multipoles [B_l^m]_c / B_r (Eq. 4 with the
+ * orientation of Eq. 3 and the angular factor of Eq. 17) for shape (mu, t),
+ * in the output order of bk_get_lm_list for (l_max, m_max) (even l).  Exact
+ * Gauss-Legendre x uniform-phase quadrature of the polynomial integrand.  The
+ * ratio [B]_d / ([B]_c B_r) gives the discreteness weights of a bin.  Errors:
+ * BK_ERR_ARG unless 0 <= m_max <= l_max <= 12, -1 <= mu <= 1, 0 < t <= 1 and
+ * k3 > 0; BK_ERR_SIZE if cap is too small. */
+bk_status bk_continuum_multipoles(int l_max, int m_max, double mu, double t, double beta, double* out, size_t cap);
+
 /* Test support: copy an intermediate device buffer of the last estimate into
  * host memory.  which = 0: Delta planes, complex [batch][nkeep][N][N] (scaled
  * by N^-3/2, planes n = 0..nkeep-1, indices u mod N); 1: D of every grid side

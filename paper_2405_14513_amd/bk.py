@@ -55,6 +55,10 @@ class bk_binning(ctypes.Structure):
     ]
 
 
+class bk_model(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("n_s", ctypes.c_double), ("f_ng", ctypes.c_double), ("beta", ctypes.c_double)]
+
+
 _lib = None
 
 _SIGS = {
@@ -80,6 +84,10 @@ _SIGS = {
     "bk_group_destroy": [ctypes.c_void_p],
     "bk_count_triangles": [ctypes.POINTER(bk_binning), ctypes.POINTER(ctypes.c_int64), ctypes.c_size_t,
                            ctypes.POINTER(ctypes.c_int64)],
+    "bk_discrete_prediction": [ctypes.POINTER(bk_binning), ctypes.POINTER(bk_model), ctypes.POINTER(ctypes.c_double),
+                               ctypes.c_size_t],
+    "bk_continuum_multipoles": [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
 }
 
 
@@ -193,6 +201,24 @@ def bk_plan_autotune(plan: int, stream: int = 0) -> list:
     out = (ctypes.c_int * 3)()
     _check(lib().bk_plan_autotune(ctypes.c_void_p(plan), ctypes.c_void_p(stream), out))
     return list(out)
+
+
+def bk_discrete_prediction(binning: bk_binning, amp: float, n_s: float, f_ng: float, beta: float) -> np.ndarray:
+    n_lm = sum(min(l, binning.m_max) + 1 for l in range(0, binning.l_max + 1, 2))
+    shape = (n_lm, binning.n_k1, binning.n_mu, binning.n_t)
+    out = np.empty(int(np.prod(shape)), dtype=np.float64)
+    model = bk_model(float(amp), float(n_s), float(f_ng), float(beta))
+    _check(lib().bk_discrete_prediction(ctypes.byref(binning), ctypes.byref(model),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return out.reshape(shape)
+
+
+def bk_continuum_multipoles(l_max: int, m_max: int, mu: float, t: float, beta: float) -> np.ndarray:
+    n_lm = sum(min(l, m_max) + 1 for l in range(0, l_max + 1, 2))
+    out = np.empty(n_lm, dtype=np.float64)
+    _check(lib().bk_continuum_multipoles(int(l_max), int(m_max), float(mu), float(t), float(beta),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return out
 
 
 def bk_count_triangles(binning: bk_binning):

@@ -368,13 +368,55 @@ extern "C" bk_status bk_count_triangles(const bk_binning* bn, int64_t* out, size
   bk::Tables T;
   std::string err;
   try {
-    err = bk::build_tables(b, bk::K3Shape(), host_threads(), &T);
+    err = bk::build_tables(b, bk::K3Shape(), host_threads(), &T, nullptr, true);
   } catch (const std::bad_alloc&) {
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
   }
   if (!err.empty()) return fail(BK_ERR_ARG, err);
   std::copy(T.bin_count.begin(), T.bin_count.end(), out);
   if (n_comb) *n_comb = T.n_combos;
+  return BK_OK;
+}
+
+extern "C" bk_status bk_discrete_prediction(const bk_binning* bn, const bk_model* model, double* out, size_t cap) {
+  g_last_error.clear();
+  if (!bn || !model || !out) return fail(BK_ERR_ARG, "null argument");
+  if (!(model->amp >= 0.0) || !std::isfinite(model->n_s) || !std::isfinite(model->f_ng) || !std::isfinite(model->beta))
+    return fail(BK_ERR_ARG, "model parameters must be finite, amp >= 0");
+  bk::FftShape sh{};
+  bk::Binning b;
+  bk_status st = check_binning(bn, &sh, &b);
+  if (st != BK_OK) return st;
+  const size_t n_out = size_t(bk::count_lm(b.l_max, b.m_max)) * b.n_k1 * b.n_mu * b.n_t;
+  if (cap < n_out) return fail(BK_ERR_SIZE, "output buffer too small");
+  bk::Model mdl;
+  mdl.amp = model->amp;
+  mdl.n_s = model->n_s;
+  mdl.f_ng = model->f_ng;
+  mdl.beta = model->beta;
+  bk::Tables T;
+  std::string err;
+  try {
+    err = bk::build_tables(b, bk::K3Shape(), host_threads(), &T, &mdl, true);
+  } catch (const std::bad_alloc&) {
+    return fail(BK_ERR_OOM, "host allocation failed while building tables");
+  }
+  if (!err.empty()) return fail(BK_ERR_ARG, err);
+  std::copy(T.model_pred.begin(), T.model_pred.end(), out);
+  return BK_OK;
+}
+
+extern "C" bk_status bk_continuum_multipoles(int l_max, int m_max, double mu, double t, double beta, double* out,
+                                             size_t cap) {
+  g_last_error.clear();
+  if (!out) return fail(BK_ERR_ARG, "null argument");
+  if (l_max < 0 || l_max > 12 || m_max < 0 || m_max > l_max) return fail(BK_ERR_ARG, "need 0 <= m_max <= l_max <= 12");
+  if (!(mu >= -1.0 && mu <= 1.0) || !(t > 0.0 && t <= 1.0) || !std::isfinite(beta))
+    return fail(BK_ERR_ARG, "need -1 <= mu <= 1, 0 < t <= 1 and a finite beta");
+  if (!(1.0 - 2.0 * t * mu + t * t > 0.0)) return fail(BK_ERR_ARG, "degenerate shape: k3 = 0");
+  const std::vector<double> v = bk::continuum_multipoles(l_max, m_max, mu, t, beta);
+  if (cap < v.size()) return fail(BK_ERR_SIZE, "output buffer too small");
+  std::copy(v.begin(), v.end(), out);
   return BK_OK;
 }
 

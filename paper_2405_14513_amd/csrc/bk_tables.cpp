@@ -59,7 +59,8 @@ int count_lm(int l_max, int m_max) {
   return n;
 }
 
-std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out) {
+std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out, const Model* model,
+                         bool geometry_only) {
   Tables& T = *out;
   T = Tables();
   T.bin = b;
@@ -236,6 +237,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   };
   std::vector<std::vector<ComboRec>> per_pt(pts.size());
   std::vector<std::vector<double>> per_pt_w(pts.size()), per_pt_d(pts.size()), per_pt_kmt(pts.size());
+  std::vector<std::vector<double>> per_pt_model(model ? pts.size() : 0);
 
   std::atomic<size_t> next_pt{0};
   std::vector<std::thread> th;
@@ -326,6 +328,17 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
               per_pt_kmt[ip].push_back(k1);
               per_pt_kmt[ip].push_back(mu);
               per_pt_kmt[ip].push_back(tt);
+              if (model) {
+                // Eqs. 15 and 17 at the combination's mean sides, mu_i = n_i / k_i
+                double pk[3], kai = 1.0;
+                for (int s3 = 0; s3 < 3; ++s3) {
+                  const double ks = std::sqrt(q[s3]);
+                  const double mui = double(n_s[s3]) / ks;
+                  pk[s3] = model->amp * std::pow(ks, model->n_s);
+                  kai *= 1.0 + model->beta * (mui * mui);
+                }
+                per_pt_model[ip].push_back(2.0 * model->f_ng * (pk[0] * pk[1] + pk[1] * pk[2] + pk[2] * pk[0]) * kai);
+              }
             }
           }
         }
@@ -338,6 +351,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   T.bin_count.assign(n_bins, 0);
   T.bin_den.assign(size_t(nlm) * n_bins, 0.0);
   std::vector<double> mean_acc(size_t(n_bins) * 3, 0.0), mean_w(n_bins, 0.0);
+  std::vector<double> model_num(model ? size_t(nlm) * n_bins : 0, 0.0);
   int64_t total = 0;
   for (size_t ip = 0; ip < pts.size(); ++ip) {
     if (!per_pt[ip].empty()) T.n_canonical_planes += 1;
@@ -348,6 +362,9 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
       for (int j = 0; j < nlm; ++j) T.bin_den[size_t(j) * n_bins + cr.bin] += wgt * per_pt_d[ip][i * nlm + j];
       for (int k = 0; k < 3; ++k) mean_acc[size_t(cr.bin) * 3 + k] += wgt * per_pt_kmt[ip][i * 3 + k];
       mean_w[cr.bin] += wgt;
+      if (model)
+        for (int j = 0; j < nlm; ++j)
+          model_num[size_t(j) * n_bins + cr.bin] += wgt * per_pt_w[ip][i * nlm + j] * per_pt_model[ip][i];
       if (cr.mult == 1) T.n_self_partner += 1;
       ++total;
     }
@@ -365,6 +382,15 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   for (int j = 0; j < nlm; ++j)
     for (int i = 0; i < n_bins; ++i)
       T.bin_empty_lm[size_t(j) * n_bins + i] = (T.bin_count[i] == 0 || T.bin_den[size_t(j) * n_bins + i] == 0.0);
+  if (model) {
+    // [B]_d = sqrt((2l+1)/4pi) sum w N_tri B / sum |Y|^2 N_tri (Eq. 13 with B in place of the estimate)
+    T.model_pred.assign(size_t(nlm) * n_bins, std::nan(""));
+    for (int j = 0; j < nlm; ++j)
+      for (int i = 0; i < n_bins; ++i)
+        if (!T.bin_empty_lm[size_t(j) * n_bins + i])
+          T.model_pred[size_t(j) * n_bins + i] = pref[j] * model_num[size_t(j) * n_bins + i] / T.bin_den[size_t(j) * n_bins + i];
+  }
+  if (geometry_only) return "";
 
   // ---- K3 work items.  Pairs are (slot A ring, slot C ring); the MFMA N
   // dimension is the slot-B ring.  Per plane triple, the kept slot-B rings of
@@ -707,6 +733,70 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     }
   }
   return "";
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iterations on P_n
+// started from the asymptotic estimate of each root.
+static void gauss_legendre(int n, std::vector<double>* x, std::vector<double>* w) {
+  x->assign(n, 0.0);
+  w->assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);  // P_n'(z)
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    (*x)[i] = -z;
+    (*x)[n - 1 - i] = z;
+    (*w)[i] = (*w)[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+std::vector<double> continuum_multipoles(int l_max, int m_max, double mu, double t, double beta) {
+  // integrand: Y*_lm(p) prod_i (1 + beta mu_i^2), a polynomial of degree
+  // l + 6 in p; 24 cos(theta) nodes and 48 phases integrate it exactly
+  const int n_theta = 24, n_phi = 48;
+  std::vector<double> x, wx;
+  gauss_legendre(n_theta, &x, &wx);
+  std::vector<int> ls, ms;
+  for (int l = 0; l <= l_max; l += 2)
+    for (int m = 0; m <= std::min(l, m_max); ++m) {
+      ls.push_back(l);
+      ms.push_back(m);
+    }
+  std::vector<double> out(ls.size(), 0.0);
+  // Eq. 3: orientation cosines of the three sides
+  const double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+  const double r3 = std::sqrt(1.0 - 2.0 * t * mu + t * t);
+  std::vector<double> P;
+  for (int it = 0; it < n_theta; ++it) {
+    const double pz = x[it];
+    const double st = std::sqrt(std::max(0.0, 1.0 - pz * pz));
+    legendre_table(l_max, pz, &P);
+    for (int ip = 0; ip < n_phi; ++ip) {
+      const double phi = 2.0 * M_PI * ip / n_phi;
+      const double px = st * std::cos(phi);
+      const double mu1 = pz;
+      const double mu2 = -mu * pz + s * px;
+      const double mu3 = -((1.0 - t * mu) * pz + t * s * px) / r3;
+      const double ang = (1.0 + beta * mu1 * mu1) * (1.0 + beta * mu2 * mu2) * (1.0 + beta * mu3 * mu3);
+      for (size_t j = 0; j < ls.size(); ++j) {
+        const double y = norm_lm(ls[j], ms[j]) * P[ls[j] * (l_max + 1) + ms[j]];
+        out[j] += wx[it] * (2.0 * M_PI / n_phi) * y * std::cos(ms[j] * phi) * ang;
+      }
+    }
+  }
+  for (size_t j = 0; j < ls.size(); ++j) out[j] *= std::sqrt((2.0 * ls[j] + 1.0) / (4.0 * M_PI));
+  return out;
 }
 
 }  // namespace bk

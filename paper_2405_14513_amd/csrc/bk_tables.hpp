@@ -85,6 +85,7 @@ struct Tables {
   std::vector<double> bin_den;           // [n_lm][n_bins]
   std::vector<double> bin_mean;          // [n_bins][3]
   std::vector<uint8_t> bin_empty_lm;     // [n_lm][n_bins] 1 if NaN
+  std::vector<double> model_pred;        // [n_lm][n_bins] discrete prediction (with a model), NaN if empty
 
   // x_perp grids.  A combination of rings whose modes reach |u_x|, |u_y| <= U
   // is summed exactly on any m x m grid with m > U_A + U_B + U_C (no closure
@@ -108,8 +109,23 @@ struct Tables {
   double dense_terms = 0.0, useful_terms = 0.0;
 };
 
-// Builds everything; returns "" on success or an error message.
-std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out);
+// The paper's model field (Eqs. 14-17): P(k) = amp k^n_s with k in units of
+// k_f, B = 2 f_NG (P1 P2 + P2 P3 + P3 P1) prod_i (1 + beta mu_i^2).
+struct Model {
+  double amp = 0.0, n_s = 0.0, f_ng = 0.0, beta = 0.0;
+};
+
+// Builds everything; returns "" on success or an error message.  With a
+// model, also the discrete prediction [B]_d per bin (model_pred).  With
+// geometry_only, stops after the per-bin geometry (no contraction tables).
+std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out,
+                         const Model* model = nullptr, bool geometry_only = false);
+
+// [B_l^m]_c / B_r for the model's redshift-space factor (Eq. 4 with Eqs. 3
+// and 17), by Gauss-Legendre x uniform-phase quadrature, exact for the
+// polynomial integrand; outputs in (l, m) order as count_lm.  The imaginary
+// parts vanish for this model (mirror symmetry in p_y).
+std::vector<double> continuum_multipoles(int l_max, int m_max, double mu, double t, double beta);
 
 // Number of (l, m) outputs for l_max, m_max (even l only).
 int count_lm(int l_max, int m_max);
