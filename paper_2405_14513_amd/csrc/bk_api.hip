@@ -170,12 +170,12 @@ constexpr bool prec_is_f32() {
 
 // LDS bytes of the contraction for a chunk of ch points (two buffers of every
 // staged slot plus the zero slot), 0 if the chunk does not divide every grid
-// level's m^2 points, gives fewer than 8 16-byte units per slot, needs more
+// level's m^2 points, gives fewer than 16 16-byte units per slot, needs more
 // staging lines than the kernel issues, or exceeds the 160 KiB of a CU.
 size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
   const size_t cs = prec == BK_F32 ? 8 : 16;
   const int units = int(size_t(ch) * cs / 16);
-  if (units < 8 || units % 8 != 0) return 0;
+  if (units < 16 || units % 16 != 0) return 0;
   for (int m : T.grid_sizes)
     if ((long(m) * m) % ch != 0) return 0;
   const size_t slot = size_t(ch) * cs;
@@ -213,14 +213,10 @@ void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
     BK_K3(float, 64, 2);
   else if (p->k3_chunk == 64)
     BK_K3(float, 64, 4);
-  else if (p->k3_chunk == 32 && t2)
-    BK_K3(float, 32, 2);
-  else if (p->k3_chunk == 32)
-    BK_K3(float, 32, 4);
   else if (t2)
-    BK_K3(float, 16, 2);
+    BK_K3(float, 32, 2);
   else
-    BK_K3(float, 16, 4);
+    BK_K3(float, 32, 4);
 }
 
 void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
@@ -229,14 +225,10 @@ void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
     BK_K3(double, 32, 2);
   else if (p->k3_chunk == 32)
     BK_K3(double, 32, 4);
-  else if (p->k3_chunk == 16 && t2)
-    BK_K3(double, 16, 2);
-  else if (p->k3_chunk == 16)
-    BK_K3(double, 16, 4);
   else if (t2)
-    BK_K3(double, 8, 2);
+    BK_K3(double, 16, 2);
   else
-    BK_K3(double, 8, 4);
+    BK_K3(double, 16, 4);
 }
 #undef BK_K3
 

@@ -212,8 +212,8 @@ struct Mfma<double> {
 // of one side's D as 16-byte units (2 float32 or 1 float64 complex points),
 // slot after slot with no padding, so whole 1 KiB lines are filled by direct
 // global-to-LDS loads (64 lanes x 16 bytes, lane i to byte 16 i).  Unit u of
-// slot s is stored at position u ^ key(s), with a 3-bit key per slot chosen on
-// the host: the 8 rows of an MFMA tile that one 16-byte LDS read serves
+// slot s is stored at position u ^ key(s), with a 4-bit key per slot chosen on
+// the host: the 16 rows of an MFMA tile that one 16-byte LDS read serves
 // together fall in different banks whenever their slots' keys differ.
 template <typename T, int CH>
 struct K3Stage {
@@ -222,7 +222,7 @@ struct K3Stage {
   static constexpr int units = CH / ppu;        // units per slot
   static constexpr int slot_bytes = CH * cs;
   static constexpr int steps = units / 4;       // 16-byte reads per operand per chunk
-  static constexpr bool valid = units >= 8 && units % 8 == 0;  // the swizzle needs 8 units per slot
+  static constexpr bool valid = units >= 16 && units % 16 == 0;  // the swizzle needs 16 units per slot
 };
 constexpr int kK3Threads = 64 * kItemsPerGroup;
 constexpr int kK3MaxLines = 8;  // 1 KiB staging lines per wave per chunk
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
                                                                  const int32_t* __restrict__ group_sides,
                                                                  double* __restrict__ S_out, long n_items_total) {
   using G = K3Stage<T, CH>;
-  static_assert(G::valid, "the swizzle needs a multiple of 8 units per slot");
+  static_assert(G::valid, "the swizzle needs a multiple of 16 units per slot");
   typedef typename Unit<T>::type unit_t;
   constexpr int kOut = 16 * TILES * kTileN;
   extern __shared__ char smem_raw[];  // starts at LDS address 0 (no static LDS): 16-byte aligned
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     if (o < data_bytes) {
       const int sl = o / G::slot_bytes;
       const int32_t e = group_sides[gd.side_begin + sl];
-      const int u = ((o - sl * G::slot_bytes) >> 4) ^ (e >> kKeyShift);
+      const int u = ((o - sl * G::slot_bytes) >> 4) ^ (e >> kKeyShift);  // key < 16 <= units
       src[i] = Db + (gside_off[e & ((1 << kKeyShift) - 1)] * G::cs + u * 16);
     }
   }
@@ -309,26 +309,31 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   // Slot C always lies on plane -(a+b) <= 0 and is read as conj D(r, a+b); on
   // the (0,0,0) triple D(r, 0) is real, so the conjugate changes nothing.
   const bool active = wave < gd.n_items;
-  // per operand: byte offsets of the even-step and odd-step reads (the swizzle
-  // flips bit 2 of the unit index when slot & 4, i.e. swaps steps q and q ^ 1)
-  int ae[TILES], ao[TILES], ce[TILES], co[TILES], be = 0, bo = 0;
-  auto offsets = [&](int slot, int& ev, int& od) {
+  // per operand: the byte offset of its read at unit step q is o[q & 3] + 64 q
+  // (unit 4 q + kq sits at position (4 q + kq) ^ key: the key's low two bits
+  // permute kq, its high two bits permute q within each group of four steps)
+  int ao[TILES][4], co[TILES][4], bo[4];
+  auto offsets = [&](int slot, int (&o)[4]) {
     const int key = slot < gd.n_sides ? group_sides[gd.side_begin + slot] >> kKeyShift : gd.zero_key;
     const int base = slot * G::slot_bytes + 16 * (kq ^ (key & 3));
-    const int d = (key & 4) ? 64 : 0;
-    ev = base + d;
-    od = base - d;
+    const int k2 = key >> 2;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = base + 64 * ((j ^ k2) - j);
   };
 #pragma unroll
-  for (int t = 0; t < TILES; ++t) ae[t] = ao[t] = ce[t] = co[t] = 0;
+  for (int j = 0; j < 4; ++j) {
+    bo[j] = 0;
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) ao[t][j] = co[t][j] = 0;
+  }
   if (active) {
     const ItemDesc& it = items[gd.item_begin + wave];
 #pragma unroll
     for (int t = 0; t < TILES; ++t) {
-      offsets(it.a_slot[16 * t + row], ae[t], ao[t]);
-      offsets(it.c_slot[16 * t + row], ce[t], co[t]);
+      offsets(it.a_slot[16 * t + row], ao[t]);
+      offsets(it.c_slot[16 * t + row], co[t]);
     }
-    offsets(it.b_slot[row], be, bo);
+    offsets(it.b_slot[row], bo);
   }
 
   typedef typename Mfma<T>::acc_t acc_t;
@@ -352,11 +357,11 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
       unit_t a_n[TILES], c_n[TILES], b_n;
       auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t& bv) {
         const int shift = 64 * q;
-        bv = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? bo : be) + shift);
+        bv = *reinterpret_cast<const unit_t*>(buf + bo[q & 3] + shift);
 #pragma unroll
         for (int t = 0; t < TILES; ++t) {
-          a[t] = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? ao[t] : ae[t]) + shift);
-          cc[t] = *reinterpret_cast<const unit_t*>(buf + ((q & 1) ? co[t] : ce[t]) + shift);
+          a[t] = *reinterpret_cast<const unit_t*>(buf + ao[t][q & 3] + shift);
+          cc[t] = *reinterpret_cast<const unit_t*>(buf + co[t][q & 3] + shift);
         }
       };
       load_step(0, a_n, c_n, b_n);

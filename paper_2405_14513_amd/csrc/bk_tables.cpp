@@ -597,13 +597,14 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         T.dense_terms += double(ppi) * kTileN * double(m) * double(m);
       }
       // LDS swizzle keys: unit u of slot s sits at u ^ key(s), and one 16-byte
-      // read serves 8 rows (or columns) together, so slots read in the same
-      // 8-row phase should carry different keys.  Greedy colouring of the
-      // slots (zero slot included) by how often two of them share a phase.
+      // read serves the 16 rows (or columns) of a tile together, so slots read
+      // by the same tile should carry different keys.  Greedy colouring of the
+      // slots (zero slot included) with kKeys keys by how often two of them
+      // share a tile.
       {
         const int nv = zero_slot + 1;
         std::vector<int32_t> w(size_t(nv) * nv, 0);
-        int phase[8];
+        int phase[kTileN];
         auto add_phase = [&](int n) {
           std::sort(phase, phase + n);
           n = int(std::unique(phase, phase + n) - phase);
@@ -613,16 +614,14 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         };
         for (int64_t ii = T.items.size() - (g1 - g0); ii < int64_t(T.items.size()); ++ii) {
           const ItemDesc& d = T.items[ii];
-          for (int h = 0; h < ppi / 8; ++h) {
-            for (int r = 0; r < 8; ++r) phase[r] = d.a_slot[8 * h + r];
-            add_phase(8);
-            for (int r = 0; r < 8; ++r) phase[r] = d.c_slot[8 * h + r];
-            add_phase(8);
+          for (int h = 0; h < ppi / kTileN; ++h) {
+            for (int r = 0; r < kTileN; ++r) phase[r] = d.a_slot[kTileN * h + r];
+            add_phase(kTileN);
+            for (int r = 0; r < kTileN; ++r) phase[r] = d.c_slot[kTileN * h + r];
+            add_phase(kTileN);
           }
-          for (int h = 0; h < kTileN / 8; ++h) {
-            for (int r = 0; r < 8; ++r) phase[r] = d.b_slot[8 * h + r];
-            add_phase(8);
-          }
+          for (int r = 0; r < kTileN; ++r) phase[r] = d.b_slot[r];
+          add_phase(kTileN);
         }
         std::vector<int64_t> deg(nv, 0);
         for (int x = 0; x < nv; ++x)
@@ -634,7 +633,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         auto best_key = [&](int x) {
           int64_t best = -1;
           int bk = 0;
-          for (int k = 0; k < 8; ++k) {
+          for (int k = 0; k < kKeys; ++k) {
             int64_t c = 0;
             for (int y = 0; y < nv; ++y)
               if (y != x && key[y] == k) c += w[size_t(x) * nv + y];

@@ -31,7 +31,8 @@ constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA r
 constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, all on one plane triple
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
 constexpr int kMaxGroupSides = 120;
-constexpr int kKeyShift = 24;       // group_sides entries: grid side in the low 24 bits, 3-bit key above  // sides a workgroup gathering several items may stage
+constexpr int kKeyShift = 24;       // group_sides entries: grid side in the low 24 bits, key above
+constexpr int kKeys = 16;           // LDS swizzle keys (16-byte units are permuted within groups of 16)  // sides a workgroup gathering several items may stage
 
 // One workgroup of the contraction kernel: up to kItemsPerGroup work items on
 // one grid (from one or a few neighbouring plane triples) that share the

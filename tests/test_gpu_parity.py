@@ -283,7 +283,7 @@ def test_autotuned_plan_matches_oracle(prec):
     try:
         est.load(t, stream)
         choices = est.autotune(stream)
-        assert choices[0] in (2, 4, 8, 16) and choices[1] in (2, 4, 8, 16) and choices[2] in (8, 16, 32, 64)
+        assert choices[0] in (2, 4, 8, 16) and choices[1] in (2, 4, 8, 16) and choices[2] in (16, 32, 64)
         err_tuned = per_multipole_error(est.multipoles()[0], ref.B)
         est.estimate(stream)
         err = per_multipole_error(est.multipoles()[0], ref.B)
