@@ -248,8 +248,9 @@ struct Unit<double> {
 // of its pair's A and C slots and of its column's B slot, forms the pair
 // products P = D_A conj(D_C) and feeds Re P, -Im P against Re D_B, Im D_B into
 // 16x16x4 MFMAs (K = the 4 points of the lanes' kq), one accumulator per row
-// tile; float32 units carry two points, i.e. two k-steps.  Each chunk's
-// partial sums are added to float64 registers.
+// tile; float32 units carry two points, i.e. two k-steps.  Float32 partial
+// sums are added to float64 registers every 128 points; float64 accumulates
+// in the MFMA registers.
 template <typename T, int CH, int TILES>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
@@ -337,11 +338,18 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   }
 
   typedef typename Mfma<T>::acc_t acc_t;
+  // float64 accumulates in the MFMA registers throughout; float32 adds its
+  // partial sums into float64 every kFlushPoints points
+  constexpr int kFlushPoints = 128;
+  constexpr int kFlush = sizeof(T) == 8 ? 0 : (kFlushPoints / CH > 1 ? kFlushPoints / CH : 1);
   double out[TILES][4];
+  acc_t acc[TILES];
 #pragma unroll
-  for (int t = 0; t < TILES; ++t)
+  for (int t = 0; t < TILES; ++t) {
+    acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[t][k] = 0.0;
+  }
 
   for (int c = 0; c < nchunks; ++c) {
     // chunk c has landed (each wave waits for its own loads, the barrier for
@@ -351,9 +359,6 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
     if (active) {
       const char* buf = smem_raw + (c & 1) * buf_bytes;
-      acc_t acc[TILES];
-#pragma unroll
-      for (int t = 0; t < TILES; ++t) acc[t] = acc_t{0, 0, 0, 0};
       unit_t a_n[TILES], c_n[TILES], b_n;
       auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t& bv) {
         const int shift = 64 * q;
@@ -392,11 +397,23 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
           for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bi, acc[t]);
         }
       }
+      if constexpr (kFlush > 0) {
+        if ((c + 1) % kFlush == 0 || c + 1 == nchunks) {
 #pragma unroll
-      for (int t = 0; t < TILES; ++t)
+          for (int t = 0; t < TILES; ++t) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][k]);
+            for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][k]);
+            acc[t] = acc_t{0, 0, 0, 0};
+          }
+        }
+      }
     }
+  }
+  if constexpr (kFlush == 0) {
+#pragma unroll
+    for (int t = 0; t < TILES; ++t)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out[t][k] = double(acc[t][k]);
   }
   if (active) {
     double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kOut;
