@@ -66,3 +66,15 @@ def test_host_errors():
     b = bk.make_binning(16, 3, 2.0, 5.0, 5, 3)
     st = bk.lib().bk_count_triangles(ctypes.byref(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 4, None)
     assert st == bk.BK_ERR_SIZE and "small" in bk.bk_last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message, before touching a device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
