@@ -208,25 +208,35 @@ int pick_tb(int n, size_t elem_bytes) {
 
 // Contraction launch for the plan's chunk and row tiles (the chunks k3_lds_bytes allows).
 void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
-  const bool t2 = p->tab.k3.pairs_per_item == 32;
-  if (p->k3_chunk == 64 && t2)
+  const int tiles = p->tab.k3.pairs_per_item / bk::kTileN;
+  const bool big = p->k3_chunk == 64;
+  if (tiles == 1 && big)
+    BK_K3(float, 64, 1);
+  else if (tiles == 1)
+    BK_K3(float, 32, 1);
+  else if (tiles == 2 && big)
     BK_K3(float, 64, 2);
-  else if (p->k3_chunk == 64)
-    BK_K3(float, 64, 4);
-  else if (t2)
+  else if (tiles == 2)
     BK_K3(float, 32, 2);
+  else if (big)
+    BK_K3(float, 64, 4);
   else
     BK_K3(float, 32, 4);
 }
 
 void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
-  const bool t2 = p->tab.k3.pairs_per_item == 32;
-  if (p->k3_chunk == 32 && t2)
+  const int tiles = p->tab.k3.pairs_per_item / bk::kTileN;
+  const bool big = p->k3_chunk == 32;
+  if (tiles == 1 && big)
+    BK_K3(double, 32, 1);
+  else if (tiles == 1)
+    BK_K3(double, 16, 1);
+  else if (tiles == 2 && big)
     BK_K3(double, 32, 2);
-  else if (p->k3_chunk == 32)
-    BK_K3(double, 32, 4);
-  else if (t2)
+  else if (tiles == 2)
     BK_K3(double, 16, 2);
+  else if (big)
+    BK_K3(double, 32, 4);
   else
     BK_K3(double, 16, 4);
 }
@@ -435,11 +445,13 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   p->device = device;
   p->max_batch = max_batch;
   p->sh = sh;
-  // Work-item shape: two row tiles per wave (32 pairs) in both precisions;
-  // four tiles pad more and, in float64, need too many registers for four
-  // waves per SIMD.  BK_K3_PAIRS=64 selects four tiles.
+  // Work-item shape: one row tile per wave (16 pairs) in both precisions.
+  // Items of 16 rows pack the (pair, slot-B window) rows more tightly than
+  // items of 32 and fill eight-item workgroups within the staged-side limit
+  // more often; that outweighs the second tile's reuse of the slot-B reads.
+  // BK_K3_PAIRS=32 or 64 selects two or four tiles per wave.
   bk::K3Shape shape;
-  shape.pairs_per_item = 32;
+  shape.pairs_per_item = 16;
   if (const char* v = std::getenv("BK_K3_PAIRS")) shape.pairs_per_item = std::atoi(v);
   if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
@@ -494,6 +506,20 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
       ring_seg.push_back(int32_t(ring_mode_uy.size()));
     }
     ring_seg_off[T.nr] = int32_t(ring_seg.size());
+    // K2 rebuilds each row's u_y from its first one: the row must be the
+    // symmetric run [-b, b] or the two runs [-b, -b + h - 1], [b - h + 1, b]
+    for (int r = 1; r <= T.nr; ++r)
+      for (int i = ring_seg_off[r - 1]; i + 1 < ring_seg_off[r]; ++i) {
+        const int m0 = ring_seg[i], cnt = ring_seg[i + 1] - m0;
+        if (cnt == 0) continue;
+        const int bmax = -ring_mode_uy[m0];
+        const bool one = cnt == 2 * bmax + 1;
+        const int h = one ? cnt : cnt / 2;
+        bool ok = bmax >= 0 && (one || cnt % 2 == 0);
+        for (int j = 0; ok && j < cnt; ++j)
+          ok = ring_mode_uy[m0 + j] == (j < h ? -bmax + j : bmax - (cnt - 1 - j));
+        if (!ok) return fail(BK_ERR_ARG, "internal: a ring row is not a pair of symmetric u_y runs");
+      }
   }
 
   std::vector<double> twd(2 * size_t(n));

@@ -146,29 +146,52 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
   __syncthreads();
   const int nrow = 2 * U + 1;
   const float inv_m = 1.0f / float(m);
+  // (t y) mod m without an integer division: |t| y < 2^18, exact in float32 after correction
+  auto mod_m = [&](int t) {
+    int e = t - int(float(t) * inv_m) * m;
+    e += e < 0 ? m : 0;
+    e -= e >= m ? m : 0;
+    return e;
+  };
   for (int q = threadIdx.x; q < nrow * tb; q += blockDim.x) {
     const int row = q / tb, l = q - row * tb;
     const int ux = row - U;
     const int y = y0 + l;
     const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + ng : ux) * ng;
     cplx<T> acc0 = {T(0), T(0)}, acc1 = {T(0), T(0)};
-    const int m0 = seg[row], m1 = seg[row + 1];
-    int k = m0;
-    // (u_y y) mod m without an integer division: u_y y < 2^18, exact in float32 after correction
-    auto term = [&](int kk) {
-      const int uy = ring_mode_uy[kk];
-      const int uyf = uy < 0 ? uy + ng : uy;
-      const int t = (uy < 0 ? uy + m : uy) * y;
-      int e = t - int(float(t) * inv_m) * m;
-      e += e < 0 ? m : 0;
-      e -= e >= m ? m : 0;
-      return cmul(Frow[uyf], tw_l[e]);
-    };
-    for (; k + 1 < m1; k += 2) {
-      acc0 = cadd(acc0, term(k));
-      acc1 = cadd(acc1, term(k + 1));
+    const int m0 = seg[row], cnt = seg[row + 1] - m0;
+    if (cnt > 0) {
+      // The row's u_y are symmetric runs: [-b, b], or [-b, -b + h - 1] and
+      // [b - h + 1, b] with h = cnt / 2 (checked when the plan is built), so
+      // they follow from the first one; the loads of four terms are issued
+      // together and the twiddle index advances by y per term.
+      const int bmax = -int(ring_mode_uy[m0]);
+      const bool one = cnt == 2 * bmax + 1;
+      const int h = one ? cnt : cnt / 2;
+      for (int run = 0; run < (one ? 1 : 2); ++run) {
+        const int start = run == 0 ? -bmax : bmax - h + 1;
+        int e = mod_m((start < 0 ? start + m : start) * y);
+        for (int j = 0; j < h; j += 4) {
+          cplx<T> f[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int uy = start + (j + i < h ? j + i : h - 1);
+            f[i] = Frow[uy < 0 ? uy + ng : uy];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (j + i < h) {
+              if (i & 1)
+                acc1 = cadd(acc1, cmul(f[i], tw_l[e]));
+              else
+                acc0 = cadd(acc0, cmul(f[i], tw_l[e]));
+            }
+            e += y;
+            e -= e >= m ? m : 0;
+          }
+        }
+      }
     }
-    if (k < m1) acc0 = cadd(acc0, term(k));
     b0[l * ls + (ux < 0 ? ux + m : ux)] = cadd(acc0, acc1);
   }
   __syncthreads();
@@ -342,11 +365,15 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   // partial sums into float64 every kFlushPoints points
   constexpr int kFlushPoints = 128;
   constexpr int kFlush = sizeof(T) == 8 ? 0 : (kFlushPoints / CH > 1 ? kFlushPoints / CH : 1);
+  // a float64 wave with one tile keeps the Re and Im products in two
+  // accumulators, so consecutive MFMAs do not wait on each other
+  constexpr int kChains = sizeof(T) == 8 && TILES == 1 ? 2 : 1;
   double out[TILES][4];
-  acc_t acc[TILES];
+  acc_t acc[TILES][kChains];
 #pragma unroll
   for (int t = 0; t < TILES; ++t) {
-    acc[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) acc[t][j] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[t][k] = 0.0;
   }
@@ -392,9 +419,9 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
           }
           const T br = b_c[2 * h], bi = b_c[2 * h + 1];
 #pragma unroll
-          for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pr[t], br, acc[t]);
+          for (int t = 0; t < TILES; ++t) acc[t][0] = Mfma<T>::step(pr[t], br, acc[t][0]);
 #pragma unroll
-          for (int t = 0; t < TILES; ++t) acc[t] = Mfma<T>::step(pn[t], bi, acc[t]);
+          for (int t = 0; t < TILES; ++t) acc[t][kChains - 1] = Mfma<T>::step(pn[t], bi, acc[t][kChains - 1]);
         }
       }
       if constexpr (kFlush > 0) {
@@ -402,8 +429,8 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
           for (int t = 0; t < TILES; ++t) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][k]);
-            acc[t] = acc_t{0, 0, 0, 0};
+            for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][0][k]);
+            acc[t][0] = acc_t{0, 0, 0, 0};
           }
         }
       }
@@ -413,7 +440,10 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
     for (int t = 0; t < TILES; ++t)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) out[t][k] = double(acc[t][k]);
+      for (int k = 0; k < 4; ++k) {
+        out[t][k] = double(acc[t][0][k]);
+        if constexpr (kChains == 2) out[t][k] += double(acc[t][1][k]);
+      }
   }
   if (active) {
     double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kOut;

@@ -66,7 +66,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   T.bin = b;
   T.k3 = k3;
   const int ppi = k3.pairs_per_item;
-  if (ppi != 32 && ppi != 64) return "pairs per work item must be 32 or 64";
+  if (ppi != 16 && ppi != 32 && ppi != 64) return "pairs per work item must be 16, 32 or 64";
   const int ng = b.ng;
   T.ng = ng;
   if (n_threads < 1) n_threads = 1;

@@ -12,7 +12,7 @@ namespace bk {
 
 // Shape of the contraction's work items (chosen per plan).
 struct K3Shape {
-  int pairs_per_item = 32;  // 32 (two row tiles per wave) or 64 (four)
+  int pairs_per_item = 16;  // 16 (one row tile per wave), 32 (two) or 64 (four)
   bool coarse_grids = true;  // evaluate each combination on the smallest alias-free x_perp grid
 };
 

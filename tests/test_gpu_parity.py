@@ -106,6 +106,22 @@ def test_parity_against_oracle(case, prec):
     assert err.max() < TOL[prec], err
 
 
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("pairs", [32, 64])
+def test_wider_work_items(pairs, prec, monkeypatch):
+    """Work items of two or four row tiles per wave (BK_K3_PAIRS) against the
+    oracle; the default is one tile."""
+    args, recipe = CASES[3]
+    _say(f"work items of {pairs} pairs, ng={args[0]} prec={prec}")
+    b, delta, ref = oracle_result(args, recipe)
+    monkeypatch.setenv("BK_K3_PAIRS", str(pairs))
+    B, counts, lms = run_gpu(args, delta, prec)
+    assert np.array_equal(counts, ref.counts)
+    err = per_multipole_error(B[0], ref.B)
+    _say(f"  max error per multipole {err.max():.3e}")
+    assert err.max() < TOL[prec], err
+
+
 def test_brute_force_small_grid_float64():
     """C1 (N_g = 16) against the direct triangle sum of Eq. 6."""
     args, recipe = CASES[0]
