@@ -161,34 +161,39 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
     cplx<T> acc0 = {T(0), T(0)}, acc1 = {T(0), T(0)};
     const int m0 = seg[row], cnt = seg[row + 1] - m0;
     if (cnt > 0) {
-      // The row's u_y are symmetric runs: [-b, b], or [-b, -b + h - 1] and
+      // The row's u_y are symmetric: [-b, b], or [-b, -b + h - 1] and
       // [b - h + 1, b] with h = cnt / 2 (checked when the plan is built), so
-      // they follow from the first one; the loads of four terms are issued
-      // together and the twiddle index advances by y per term.
+      // they follow from the first one.  The terms of u_y = v and -v share
+      // one twiddle: F(v) w^{v y} + F(-v) w^{-v y} = c S - i s A with
+      // S = F(v) + F(-v), A = F(v) - F(-v), w^{v y} = c - i s; the twiddle
+      // index advances by y per v and the loads of two v are issued together.
       const int bmax = -int(ring_mode_uy[m0]);
       const bool one = cnt == 2 * bmax + 1;
-      const int h = one ? cnt : cnt / 2;
-      for (int run = 0; run < (one ? 1 : 2); ++run) {
-        const int start = run == 0 ? -bmax : bmax - h + 1;
-        int e = mod_m((start < 0 ? start + m : start) * y);
-        for (int j = 0; j < h; j += 4) {
-          cplx<T> f[4];
+      const int vlo = one ? 1 : bmax - cnt / 2 + 1;
+      if (one) acc0 = Frow[0];
+      const int nv = bmax - vlo + 1;
+      int e = mod_m(vlo * y);
+      for (int j = 0; j < nv; j += 2) {
+        cplx<T> fp[2], fm[2];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int uy = start + (j + i < h ? j + i : h - 1);
-            f[i] = Frow[uy < 0 ? uy + ng : uy];
-          }
+        for (int i = 0; i < 2; ++i) {
+          const int v = vlo + (j + i < nv ? j + i : nv - 1);
+          fp[i] = Frow[v];
+          fm[i] = Frow[ng - v];
+        }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (j + i < h) {
-              if (i & 1)
-                acc1 = cadd(acc1, cmul(f[i], tw_l[e]));
-              else
-                acc0 = cadd(acc0, cmul(f[i], tw_l[e]));
-            }
-            e += y;
-            e -= e >= m ? m : 0;
+        for (int i = 0; i < 2; ++i) {
+          if (j + i < nv) {
+            const cplx<T> w = tw_l[e];  // (c, -s)
+            const cplx<T> sp = cadd(fp[i], fm[i]), am = csub(fp[i], fm[i]);
+            const cplx<T> t = {w.x * sp.x - w.y * am.y, w.x * sp.y + w.y * am.x};
+            if (i == 0)
+              acc0 = cadd(acc0, t);
+            else
+              acc1 = cadd(acc1, t);
           }
+          e += y;
+          e -= e >= m ? m : 0;
         }
       }
     }

@@ -27,10 +27,13 @@ struct Binning {
 
 // Sizes of the K3 work decomposition.
 constexpr int kTileN = 16;           // third-slot rings per work item (MFMA N)
-constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 2 or 4 tiles
-constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, all on one plane triple
+constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 1, 2 or 4 tiles
+constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, on neighbouring plane triples
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
-constexpr int kMaxGroupSides = 120;
+// Staged sides per workgroup: with the zero slot, two buffers of 105 slots of
+// 256 bytes (32 float32 or 16 float64 points) take 53 760 bytes, so three
+// workgroups share the 160 KiB of LDS of a compute unit.
+constexpr int kMaxGroupSides = 104;
 constexpr int kKeyShift = 24;       // group_sides entries: grid side in the low 24 bits, key above
 constexpr int kKeys = 16;           // LDS swizzle keys (16-byte units are permuted within groups of 16)  // sides a workgroup gathering several items may stage
 
