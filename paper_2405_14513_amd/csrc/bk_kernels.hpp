@@ -153,12 +153,16 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
     e -= e >= m ? m : 0;
     return e;
   };
-  for (int q = threadIdx.x; q < nrow * tb; q += blockDim.x) {
-    const int row = q / tb, l = q - row * tb;
+  // one item = one row u_x and the two columns y0 + l, y0 + l + tb / 2
+  // (one column when tb = 1)
+  const int half = tb > 1 ? tb / 2 : 1;
+  for (int q = threadIdx.x; q < nrow * half; q += blockDim.x) {
+    const int row = q / half, l = q - row * half;
     const int ux = row - U;
-    const int y = y0 + l;
+    const int nc = tb > 1 ? 2 : 1;
+    int yc[2] = {y0 + l, y0 + l + half};
     const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + ng : ux) * ng;
-    cplx<T> acc0 = {T(0), T(0)}, acc1 = {T(0), T(0)};
+    cplx<T> acc[2] = {{T(0), T(0)}, {T(0), T(0)}};
     const int m0 = seg[row], cnt = seg[row + 1] - m0;
     if (cnt > 0) {
       // The row's u_y are symmetric: [-b, b], or [-b, -b + h - 1] and
@@ -166,13 +170,13 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
       // they follow from the first one.  The terms of u_y = v and -v share
       // one twiddle: F(v) w^{v y} + F(-v) w^{-v y} = c S - i s A with
       // S = F(v) + F(-v), A = F(v) - F(-v), w^{v y} = c - i s; the twiddle
-      // index advances by y per v and the loads of two v are issued together.
+      // index advances by y per v, and the loads of two v are issued together.
       const int bmax = -int(ring_mode_uy[m0]);
       const bool one = cnt == 2 * bmax + 1;
       const int vlo = one ? 1 : bmax - cnt / 2 + 1;
-      if (one) acc0 = Frow[0];
+      if (one) acc[0] = acc[1] = Frow[0];
       const int nv = bmax - vlo + 1;
-      int e = mod_m(vlo * y);
+      int e[2] = {mod_m(vlo * yc[0]), mod_m(vlo * yc[1])};
       for (int j = 0; j < nv; j += 2) {
         cplx<T> fp[2], fm[2];
 #pragma unroll
@@ -183,21 +187,21 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          if (j + i < nv) {
-            const cplx<T> w = tw_l[e];  // (c, -s)
-            const cplx<T> sp = cadd(fp[i], fm[i]), am = csub(fp[i], fm[i]);
-            const cplx<T> t = {w.x * sp.x - w.y * am.y, w.x * sp.y + w.y * am.x};
-            if (i == 0)
-              acc0 = cadd(acc0, t);
-            else
-              acc1 = cadd(acc1, t);
+          const cplx<T> sp = cadd(fp[i], fm[i]), am = csub(fp[i], fm[i]);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (j + i < nv) {
+              const cplx<T> w = tw_l[e[c]];  // (c, -s)
+              acc[c] = cadd(acc[c], cplx<T>{w.x * sp.x - w.y * am.y, w.x * sp.y + w.y * am.x});
+            }
+            e[c] += yc[c];
+            e[c] -= e[c] >= m ? m : 0;
           }
-          e += y;
-          e -= e >= m ? m : 0;
         }
       }
     }
-    b0[l * ls + (ux < 0 ? ux + m : ux)] = cadd(acc0, acc1);
+    const int pos = ux < 0 ? ux + m : ux;
+    for (int c = 0; c < nc; ++c) b0[(l + c * half) * ls + pos] = acc[c];
   }
   __syncthreads();
   cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
