@@ -38,7 +38,7 @@ BATCHED = [(64, 24), (96, 24), (128, 16)]
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("bk_kernels.hpp", "bk_fft.hpp", "bk_tables.cpp", "bk_api.hip"):
+    for name in ("bk_kernels.hpp", "bk_fft.hpp", "bk_tables.hpp", "bk_tables.cpp", "bk_api.hip"):
         with open(os.path.join(ROOT, "paper_2405_14513_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -85,7 +85,12 @@ typedef struct {
  * in float32, blocked float32 partial sums combined in float64) or float64
  * (BK_F64: every step in float64).  The final per-bin sums are float64 in both.
  * Setting the environment variable BK_FULL_GRID=1 sums every combination on
- * the full N_g x N_g grid instead (same results up to rounding; slower). */
+ * the full N_g x N_g grid instead (same results up to rounding; slower).
+ * The contraction's work-item shape can be overridden the same way (results
+ * equal up to rounding): BK_K3_PAIRS=32 or 64 (ring pairs per item, one item
+ * per wave), BK_K3_ITEMS=1 or 2 (16-pair items per wave, default 2) and
+ * BK_K3_SIDES (staged sides per workgroup, 1..254).  An invalid combination
+ * fails with BK_ERR_ARG. */
 bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int max_batch, bk_plan* out);
 bk_status bk_plan_destroy(bk_plan plan);
 

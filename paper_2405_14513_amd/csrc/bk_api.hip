@@ -179,7 +179,7 @@ size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
   for (int m : T.grid_sizes)
     if ((long(m) * m) % ch != 0) return 0;
   const size_t slot = size_t(ch) * cs;
-  if (size_t(T.max_group_sides - 1) * slot > size_t(bk::kK3MaxLines) * bk::kItemsPerGroup * 1024) return 0;
+  if (size_t(T.max_group_sides - 1) * slot > size_t(bk::kK3MaxLines) * bk::kWavesPerGroup * 1024) return 0;
   const size_t lds = 2 * size_t(T.max_group_sides) * slot;
   return lds <= 163840 ? lds : 0;
 }
@@ -201,44 +201,38 @@ int pick_tb(int n, size_t elem_bytes) {
   return tb;
 }
 
-#define BK_K3(TT, CHV, TV)                                                                                       \
-  hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TV>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,            \
+#define BK_K3(TT, CHV, TPI, IPW)                                                                                 \
+  hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,      \
                      long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides, p->d_S,           \
                      p->n_items)
 
-// Contraction launch for the plan's chunk and row tiles (the chunks k3_lds_bytes allows).
-void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
-  const int tiles = p->tab.k3.pairs_per_item / bk::kTileN;
-  const bool big = p->k3_chunk == 64;
-  if (tiles == 1 && big)
-    BK_K3(float, 64, 1);
-  else if (tiles == 1)
-    BK_K3(float, 32, 1);
-  else if (tiles == 2 && big)
-    BK_K3(float, 64, 2);
-  else if (tiles == 2)
-    BK_K3(float, 32, 2);
-  else if (big)
-    BK_K3(float, 64, 4);
+// Contraction launch for the plan's item shape (row tiles per item, items per wave).
+template <typename T, int CH>
+void launch_k3_shape(bk_plan p, const bk::cplx<T>* D, dim3 g3, hipStream_t st) {
+  const int tpi = p->tab.k3.pairs_per_item / bk::kTileN;
+  if (p->tab.k3.items_per_wave == 2)
+    BK_K3(T, CH, 1, 2);
+  else if (tpi == 1)
+    BK_K3(T, CH, 1, 1);
+  else if (tpi == 2)
+    BK_K3(T, CH, 2, 1);
   else
-    BK_K3(float, 32, 4);
+    BK_K3(T, CH, 4, 1);
+}
+
+// ... and the plan's chunk (one of the two k3_lds_bytes allows per precision).
+void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
+  if (p->k3_chunk == 64)
+    launch_k3_shape<float, 64>(p, D, g3, st);
+  else
+    launch_k3_shape<float, 32>(p, D, g3, st);
 }
 
 void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
-  const int tiles = p->tab.k3.pairs_per_item / bk::kTileN;
-  const bool big = p->k3_chunk == 32;
-  if (tiles == 1 && big)
-    BK_K3(double, 32, 1);
-  else if (tiles == 1)
-    BK_K3(double, 16, 1);
-  else if (tiles == 2 && big)
-    BK_K3(double, 32, 2);
-  else if (tiles == 2)
-    BK_K3(double, 16, 2);
-  else if (big)
-    BK_K3(double, 32, 4);
+  if (p->k3_chunk == 32)
+    launch_k3_shape<double, 32>(p, D, g3, st);
   else
-    BK_K3(double, 16, 4);
+    launch_k3_shape<double, 16>(p, D, g3, st);
 }
 #undef BK_K3
 
@@ -445,14 +439,25 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   p->device = device;
   p->max_batch = max_batch;
   p->sh = sh;
-  // Work-item shape: one row tile per wave (16 pairs) in both precisions.
-  // Items of 16 rows pack the (pair, slot-B window) rows more tightly than
-  // items of 32 and fill eight-item workgroups within the staged-side limit
-  // more often; that outweighs the second tile's reuse of the slot-B reads.
-  // BK_K3_PAIRS=32 or 64 selects two or four tiles per wave.
+  // Work-item shape: items of 16 pairs (one row tile) pack the (pair,
+  // slot-B window) rows tightly; two per wave make workgroups of 16 items,
+  // which share their staged sides: about 0.26 staged bytes per padded term
+  // (float32) against 0.33 with eight items, and the contraction is close to
+  // bound by that traffic.  Two buffers of 151 slots of 256 bytes take
+  // 77 312 bytes of LDS: two workgroups per compute unit.  With one item per
+  // wave, 104 sides (53 760 bytes) let three workgroups share a compute unit.
+  // BK_K3_PAIRS=32 or 64 selects items of two or four tiles (one per wave),
+  // BK_K3_ITEMS=1 one 16-pair item per wave; BK_K3_SIDES overrides the cap.
   bk::K3Shape shape;
   shape.pairs_per_item = 16;
-  if (const char* v = std::getenv("BK_K3_PAIRS")) shape.pairs_per_item = std::atoi(v);
+  shape.items_per_wave = 2;
+  if (const char* v = std::getenv("BK_K3_PAIRS")) {
+    shape.pairs_per_item = std::atoi(v);
+    if (shape.pairs_per_item != 16) shape.items_per_wave = 1;
+  }
+  if (const char* v = std::getenv("BK_K3_ITEMS")) shape.items_per_wave = std::atoi(v);
+  shape.max_group_sides = shape.items_per_wave == 2 ? 150 : 104;
+  if (const char* v = std::getenv("BK_K3_SIDES")) shape.max_group_sides = std::atoi(v);
   if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
   try {

@@ -256,7 +256,7 @@ struct K3Stage {
   static constexpr int steps = units / 4;       // 16-byte reads per operand per chunk
   static constexpr bool valid = units >= 16 && units % 16 == 0;  // the swizzle needs 16 units per slot
 };
-constexpr int kK3Threads = 64 * kItemsPerGroup;
+constexpr int kK3Threads = 64 * kWavesPerGroup;
 constexpr int kK3MaxLines = 8;  // 1 KiB staging lines per wave per chunk
 
 typedef double f64x2v __attribute__((ext_vector_type(2)));
@@ -273,8 +273,9 @@ struct Unit<double> {
 };
 
 // One block = one GroupDesc (items on one grid of m x m points that share
-// the sides staged in LDS), one wave per work item of 16 * TILES ring pairs
-// x 16 slot-B rings.  The m^2 points are visited in chunks of CH: while the
+// the sides staged in LDS); wave w contracts items IPW w .. IPW w + IPW - 1,
+// each 16 TPI ring pairs x 16 slot-B rings (TPI row tiles sharing the slot-B
+// reads), TILES = TPI IPW row tiles in all.  The m^2 points are visited in chunks of CH: while the
 // waves contract chunk c from one LDS buffer, the direct loads of chunk c+1
 // fill the other.  Per 16-byte unit step, lane (row, kq) reads unit 4 q + kq
 // of its pair's A and C slots and of its column's B slot, forms the pair
@@ -283,7 +284,7 @@ struct Unit<double> {
 // tile; float32 units carry two points, i.e. two k-steps.  Float32 partial
 // sums are added to float64 registers every 128 points; float64 accumulates
 // in the MFMA registers.
-template <typename T, int CH, int TILES>
+template <typename T, int CH, int TPI, int IPW>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
                                                                  const GroupDesc* __restrict__ groups,
@@ -293,7 +294,8 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   using G = K3Stage<T, CH>;
   static_assert(G::valid, "the swizzle needs a multiple of 16 units per slot");
   typedef typename Unit<T>::type unit_t;
-  constexpr int kOut = 16 * TILES * kTileN;
+  constexpr int TILES = TPI * IPW;
+  constexpr int kOut = 16 * TPI * kTileN;  // outputs per item
   extern __shared__ char smem_raw[];  // starts at LDS address 0 (no static LDS): 16-byte aligned
   const GroupDesc gd = groups[blockIdx.x];
   const int b = blockIdx.y;
@@ -312,13 +314,13 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     reinterpret_cast<uint4*>(smem_raw + buf_bytes + data_bytes)[i] = make_uint4(0u, 0u, 0u, 0u);
   }
 
-  // this wave's staging lines (wave, wave + 8, ...): per lane, the global
+  // this wave's staging lines (wave, wave + waves, ...): per lane, the global
   // source of the 16 bytes it moves; null for lanes past the last slot
   const int n_lines = (data_bytes + 1023) >> 10;
   const char* src[kK3MaxLines];
 #pragma unroll
   for (int i = 0; i < kK3MaxLines; ++i) {
-    const int o = (wave + 8 * i) * 1024 + lane * 16;
+    const int o = (wave + kWavesPerGroup * i) * 1024 + lane * 16;
     src[i] = nullptr;
     if (o < data_bytes) {
       const int sl = o / G::slot_bytes;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     char* dst = smem_raw + sel * buf_bytes;
 #pragma unroll
     for (int i = 0; i < kK3MaxLines; ++i) {
-      const int line = wave + 8 * i;
+      const int line = wave + kWavesPerGroup * i;
       if (line < n_lines && src[i])
         __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(src[i] + long(chunk) * G::slot_bytes),
                                          reinterpret_cast<uint4*>(dst + line * 1024), 16, 0, 0);
@@ -341,11 +343,12 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 
   // Slot C always lies on plane -(a+b) <= 0 and is read as conj D(r, a+b); on
   // the (0,0,0) triple D(r, 0) is real, so the conjugate changes nothing.
-  const bool active = wave < gd.n_items;
+  const int item0 = wave * IPW;  // this wave's first item in the group
+  const bool active = item0 < gd.n_items;
   // per operand: the byte offset of its read at unit step q is o[q & 3] + 64 q
   // (unit 4 q + kq sits at position (4 q + kq) ^ key: the key's low two bits
   // permute kq, its high two bits permute q within each group of four steps)
-  int ao[TILES][4], co[TILES][4], bo[4];
+  int ao[TILES][4], co[TILES][4], bo[IPW][4];
   auto offsets = [&](int slot, int (&o)[4]) {
     const int key = slot < gd.n_sides ? group_sides[gd.side_begin + slot] >> kKeyShift : gd.zero_key;
     const int base = slot * G::slot_bytes + 16 * (kq ^ (key & 3));
@@ -353,20 +356,17 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
     for (int j = 0; j < 4; ++j) o[j] = base + 64 * ((j ^ k2) - j);
   };
+  // an item past the group's last reads the zero slot and is not written
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    bo[j] = 0;
+  for (int i = 0; i < IPW; ++i) {
+    const bool live = item0 + i < gd.n_items;
+    const ItemDesc* it = live ? &items[gd.item_begin + item0 + i] : nullptr;
 #pragma unroll
-    for (int t = 0; t < TILES; ++t) ao[t][j] = co[t][j] = 0;
-  }
-  if (active) {
-    const ItemDesc& it = items[gd.item_begin + wave];
-#pragma unroll
-    for (int t = 0; t < TILES; ++t) {
-      offsets(it.a_slot[16 * t + row], ao[t]);
-      offsets(it.c_slot[16 * t + row], co[t]);
+    for (int u = 0; u < TPI; ++u) {
+      offsets(live ? it->a_slot[16 * u + row] : gd.n_sides, ao[TPI * i + u]);
+      offsets(live ? it->c_slot[16 * u + row] : gd.n_sides, co[TPI * i + u]);
     }
-    offsets(it.b_slot[row], bo);
+    offsets(live ? it->b_slot[row] : gd.n_sides, bo[i]);
   }
 
   typedef typename Mfma<T>::acc_t acc_t;
@@ -395,10 +395,11 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
     if (active) {
       const char* buf = smem_raw + (c & 1) * buf_bytes;
-      unit_t a_n[TILES], c_n[TILES], b_n;
-      auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t& bv) {
+      unit_t a_n[TILES], c_n[TILES], b_n[IPW];
+      auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t* bv) {
         const int shift = 64 * q;
-        bv = *reinterpret_cast<const unit_t*>(buf + bo[q & 3] + shift);
+#pragma unroll
+        for (int i = 0; i < IPW; ++i) bv[i] = *reinterpret_cast<const unit_t*>(buf + bo[i][q & 3] + shift);
 #pragma unroll
         for (int t = 0; t < TILES; ++t) {
           a[t] = *reinterpret_cast<const unit_t*>(buf + ao[t][q & 3] + shift);
@@ -408,12 +409,14 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
       load_step(0, a_n, c_n, b_n);
 #pragma unroll
       for (int q = 0; q < G::steps; ++q) {
-        unit_t a_c[TILES], c_c[TILES], b_c = b_n;
+        unit_t a_c[TILES], c_c[TILES], b_c[IPW];
 #pragma unroll
         for (int t = 0; t < TILES; ++t) {
           a_c[t] = a_n[t];
           c_c[t] = c_n[t];
         }
+#pragma unroll
+        for (int i = 0; i < IPW; ++i) b_c[i] = b_n[i];
         if (q + 1 < G::steps) load_step(q + 1, a_n, c_n, b_n);
 #pragma unroll
         for (int h = 0; h < G::ppu; ++h) {
@@ -426,11 +429,11 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
             pr[t] = ar * cr + ai * ci;
             pn[t] = ar * ci - ai * cr;
           }
-          const T br = b_c[2 * h], bi = b_c[2 * h + 1];
 #pragma unroll
-          for (int t = 0; t < TILES; ++t) acc[t][0] = Mfma<T>::step(pr[t], br, acc[t][0]);
+          for (int t = 0; t < TILES; ++t) acc[t][0] = Mfma<T>::step(pr[t], b_c[t / TPI][2 * h], acc[t][0]);
 #pragma unroll
-          for (int t = 0; t < TILES; ++t) acc[t][kChains - 1] = Mfma<T>::step(pn[t], bi, acc[t][kChains - 1]);
+          for (int t = 0; t < TILES; ++t)
+            acc[t][kChains - 1] = Mfma<T>::step(pn[t], b_c[t / TPI][2 * h + 1], acc[t][kChains - 1]);
         }
       }
       if constexpr (kFlush > 0) {
@@ -454,12 +457,14 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
         if constexpr (kChains == 2) out[t][k] += double(acc[t][1][k]);
       }
   }
-  if (active) {
-    double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + wave) * kOut;
 #pragma unroll
-    for (int t = 0; t < TILES; ++t)
+  for (int i = 0; i < IPW; ++i) {
+    if (item0 + i >= gd.n_items) break;
+    double* o = S_out + (size_t(b) * n_items_total + gd.item_begin + item0 + i) * kOut;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o[(16 * t + Mfma<T>::out_row(kq, k)) * kTileN + row] = out[t][k];
+    for (int u = 0; u < TPI; ++u)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[(16 * u + Mfma<T>::out_row(kq, k)) * kTileN + row] = out[TPI * i + u][k];
   }
 }
 

@@ -67,6 +67,9 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   T.k3 = k3;
   const int ppi = k3.pairs_per_item;
   if (ppi != 16 && ppi != 32 && ppi != 64) return "pairs per work item must be 16, 32 or 64";
+  const int ipw = k3.items_per_wave;
+  if (ipw != 1 && !(ipw == 2 && ppi == 16)) return "items per wave must be 1, or 2 with 16 pairs per item";
+  if (k3.max_group_sides < 1 || k3.max_group_sides > kMaxGroupSidesLimit) return "staged sides per workgroup out of range";
   const int ng = b.ng;
   T.ng = ng;
   if (n_threads < 1) n_threads = 1;
@@ -400,8 +403,8 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   // from the largest down; the free rows of an item are then filled with
   // segments of smaller grids that fit its window (a larger grid is still
   // exact).  Items of one grid are finally gathered into workgroups of up to
-  // kItemsPerGroup across neighbouring plane triples while the staged sides
-  // stay within kMaxGroupSides.
+  // kWavesPerGroup * items_per_wave across neighbouring plane triples while
+  // the staged sides stay within max_group_sides.
   const int n_levels = int(T.grid_sizes.size());
   struct Seg {
     int level, ra, rc, lo, hi;
@@ -538,7 +541,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
       std::vector<int32_t> gs;  // sorted, unique
       std::vector<uint32_t> b_used;
       size_t g1 = g0;
-      while (g1 < its.size() && g1 - g0 < size_t(kItemsPerGroup)) {
+      while (g1 < its.size() && g1 - g0 < size_t(kWavesPerGroup * ipw)) {
         std::vector<int32_t> add;
         uint32_t bu = 0;
         item_sides(its[g1], &add, &bu);
@@ -546,7 +549,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         merged.insert(merged.end(), add.begin(), add.end());
         std::sort(merged.begin(), merged.end());
         merged.erase(std::unique(merged.begin(), merged.end()), merged.end());
-        if (g1 > g0 && int(merged.size()) > kMaxGroupSides) break;
+        if (g1 > g0 && int(merged.size()) > k3.max_group_sides) break;
         gs.swap(merged);
         b_used.push_back(bu);
         ++g1;

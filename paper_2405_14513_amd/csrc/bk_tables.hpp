@@ -10,9 +10,14 @@
 
 namespace bk {
 
-// Shape of the contraction's work items (chosen per plan).
+// Shape of the contraction's work items (chosen per plan).  A work item is
+// pairs_per_item ring pairs x kTileN slot-B rings; a wave contracts
+// items_per_wave items (pairs_per_item / 16 row tiles each); a workgroup of
+// kWavesPerGroup waves stages at most max_group_sides sides for its items.
 struct K3Shape {
-  int pairs_per_item = 16;  // 16 (one row tile per wave), 32 (two) or 64 (four)
+  int pairs_per_item = 16;   // 16, 32 or 64
+  int items_per_wave = 1;    // 1 or 2 (2 only with 16 pairs)
+  int max_group_sides = 104;
   bool coarse_grids = true;  // evaluate each combination on the smallest alias-free x_perp grid
 };
 
@@ -28,16 +33,13 @@ struct Binning {
 // Sizes of the K3 work decomposition.
 constexpr int kTileN = 16;           // third-slot rings per work item (MFMA N)
 constexpr int kMaxPairsPerItem = 64;  // ring pairs per work item: 16 per MFMA row tile, 1, 2 or 4 tiles
-constexpr int kItemsPerGroup = 8;     // work items (waves) per workgroup, on neighbouring plane triples
+constexpr int kWavesPerGroup = 8;     // waves per workgroup (items on neighbouring plane triples)
 constexpr int kChunkMax = 64;      // x_perp points staged in LDS per step (32 or 64)
-// Staged sides per workgroup: with the zero slot, two buffers of 105 slots of
-// 256 bytes (32 float32 or 16 float64 points) take 53 760 bytes, so three
-// workgroups share the 160 KiB of LDS of a compute unit.
-constexpr int kMaxGroupSides = 104;
+constexpr int kMaxGroupSidesLimit = 254;  // LDS slots are bytes, the zero slot included
 constexpr int kKeyShift = 24;       // group_sides entries: grid side in the low 24 bits, key above
 constexpr int kKeys = 16;           // LDS swizzle keys (16-byte units are permuted within groups of 16)  // sides a workgroup gathering several items may stage
 
-// One workgroup of the contraction kernel: up to kItemsPerGroup work items on
+// One workgroup of the contraction kernel: up to kWavesPerGroup * items_per_wave work items on
 // one grid (from one or a few neighbouring plane triples) that share the
 // sides staged in LDS.
 struct GroupDesc {

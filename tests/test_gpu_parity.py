@@ -106,15 +106,22 @@ def test_parity_against_oracle(case, prec):
     assert err.max() < TOL[prec], err
 
 
+WORK_SHAPES = {"items1": {"BK_K3_ITEMS": "1"}, "pairs32": {"BK_K3_PAIRS": "32"},
+               "pairs64": {"BK_K3_PAIRS": "64"}, "sides48": {"BK_K3_SIDES": "48"}}
+
+
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
-@pytest.mark.parametrize("pairs", [32, 64])
-def test_wider_work_items(pairs, prec, monkeypatch):
-    """Work items of two or four row tiles per wave (BK_K3_PAIRS) against the
-    oracle; the default is one tile."""
+@pytest.mark.parametrize("shape", list(WORK_SHAPES))
+def test_other_work_item_shapes(shape, prec, monkeypatch):
+    """The contraction's other work-item shapes against the oracle: one 16-pair
+    item per wave, items of two or four row tiles sharing their slot-B reads,
+    and a small staged-side cap (many workgroups of few items); the default is
+    two 16-pair items per wave."""
     args, recipe = CASES[3]
-    _say(f"work items of {pairs} pairs, ng={args[0]} prec={prec}")
+    _say(f"work item shape {shape}, ng={args[0]} prec={prec}")
     b, delta, ref = oracle_result(args, recipe)
-    monkeypatch.setenv("BK_K3_PAIRS", str(pairs))
+    for k, v in WORK_SHAPES[shape].items():
+        monkeypatch.setenv(k, v)
     B, counts, lms = run_gpu(args, delta, prec)
     assert np.array_equal(counts, ref.counts)
     err = per_multipole_error(B[0], ref.B)
@@ -198,6 +205,19 @@ def test_error_paths():
         bk.bk_plan_destroy(plan)
     with pytest.raises(bk.BkError) as e:
         bk.bk_plan_create(bk.make_binning(16, 3, 2.0, 5.0, 5, 3), 7, 0, 1)
+    assert e.value.status == bk.BK_ERR_ARG
+
+
+@pytest.mark.parametrize("env", [{"BK_K3_ITEMS": "3"}, {"BK_K3_PAIRS": "32", "BK_K3_ITEMS": "2"},
+                                 {"BK_K3_PAIRS": "48"}, {"BK_K3_SIDES": "0"}, {"BK_K3_SIDES": "255"}])
+def test_invalid_work_item_shape_is_rejected(env, monkeypatch):
+    _torch()
+    from paper_2405_14513_amd import bk
+
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    with pytest.raises(bk.BkError) as e:
+        bk.bk_plan_create(bk.make_binning(16, 3, 2.0, 5.0, 5, 3), bk.BK_F32, 0, 1)
     assert e.value.status == bk.BK_ERR_ARG
 
 
