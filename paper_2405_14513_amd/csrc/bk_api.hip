@@ -617,15 +617,15 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   std::vector<int64_t>().swap(T.combo_slot);
 
   {
-    // largest chunk whose two staging buffers fit 64 KiB (two workgroups per
-    // CU), else the smallest valid one
+    // largest chunk whose two staging buffers fit 80 KiB (at least two
+    // workgroups per CU), else the smallest valid one
     p->k3_chunk = 0;
     for (int ch : {64, 32, 16, 8}) {
       const size_t lds = k3_lds_bytes(T, prec, ch);
-      if (lds && (lds <= 65536 || p->k3_chunk == 0)) {
+      if (lds && (lds <= 81920 || p->k3_chunk == 0)) {
         p->k3_chunk = ch;
         p->lds_k3 = lds;
-        if (lds <= 65536) break;
+        if (lds <= 81920) break;
       }
     }
     if (p->k3_chunk == 0) {
