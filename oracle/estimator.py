@@ -18,8 +18,16 @@ Both return T(c) = B_hat(c) N_tri(c) = (1/V) sum_{u,v,w} Delta Delta Delta
 delta_K(u+v+w) = (1/(V N_g^2)) sum_x D D D, the quantity that enters the
 numerator of Eq. 13.  ``multipoles`` then accumulates Eq. 13:
     num_lm[bin] += w_lm(c) T(c),  den_lm[bin] += d_lm(c) N_tri(c),
-    count[bin] += N_tri(c),      B_lm = sqrt((2l+1)/(4 pi)) Re(num)/den,
+    count[bin] += N_tri(c),      B_lm = sqrt((2l+1)/(4 pi)) num/den,
 with NaN for bins that receive no combination.
+
+Reading for odd l (the paper shows even l only): a combination c and its
+partner with every n negated carry conjugate sums, T(c-bar) = conj T(c) for a
+real field, and mirror-averaged weights of opposite sign for odd l
+(p_z -> -p_z and phi -> pi - phi give (-1)^l), so num_lm is real for even l
+and imaginary for odd l.  The reported B_lm is Re(num)/den for even l and
+Im(num)/den for odd l (times the prefactor); the other part vanishes
+identically.
 """
 from __future__ import annotations
 
@@ -150,6 +158,16 @@ class Multipoles:
     den: np.ndarray  # (n_lm, n_bins)
 
 
+def _finish(lms, num, den):
+    """sqrt((2l+1)/(4 pi)) num/den: the real part for even l, the imaginary
+    part for odd l (the other vanishes, see the module notes)."""
+    pref = np.array([math.sqrt((2 * l + 1) / (4.0 * math.pi)) for l, _ in lms])
+    odd = np.array([l % 2 == 1 for l, _ in lms])
+    part = np.where(odd[:, None], num.imag, num.real)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return pref[:, None] * part / den
+
+
 def multipoles(geom: Geometry, T: np.ndarray) -> Multipoles:
     """Second-level binning of Eq. 13, accumulated per combination."""
     b = geom.binning
@@ -163,9 +181,7 @@ def multipoles(geom: Geometry, T: np.ndarray) -> Multipoles:
         np.add.at(den[j], c.bin, c.d[:, j] * c.ntri.astype(np.float64))
     counts = np.zeros(nb, dtype=np.int64)
     np.add.at(counts, c.bin, c.ntri)
-    pref = np.array([math.sqrt((2 * l + 1) / (4.0 * math.pi)) for l, _ in lms])
-    with np.errstate(invalid="ignore", divide="ignore"):
-        B = pref[:, None] * num.real / den
+    B = _finish(lms, num, den)
     B[:, counts == 0] = np.nan
     B[den == 0.0] = np.nan
     shape = (len(lms), b.n_k1, b.n_mu, b.n_t)
@@ -252,9 +268,7 @@ def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, ch
         num += pnum
         den += pden
         counts += pc
-    pref = np.array([math.sqrt((2 * l + 1) / (4.0 * math.pi)) for l, _ in lms])
-    with np.errstate(invalid="ignore", divide="ignore"):
-        B = pref[:, None] * num.real / den
+    B = _finish(lms, num, den)
     B[:, counts == 0] = np.nan
     B[den == 0.0] = np.nan
     shape = (len(lms), binning.n_k1, binning.n_mu, binning.n_t)

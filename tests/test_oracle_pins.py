@@ -230,6 +230,85 @@ def test_three_plane_waves_closed_form():
     assert np.nanmax(np.abs(vals)) < 1e-9 * np.max(np.abs(want))
 
 
+# --- odd l: the imaginary part of Eq. 13 (reading in oracle/estimator.py) ---------
+
+C1_ODD = Binning(16, 3, 2.0, 5.0, 5, 3, even_l_only=False)
+
+
+def _partner_index(geom):
+    """For every combination, the index of its n -> -n partner."""
+    sides = geom.sides
+    key = {}
+    trio = geom.combos.sides
+    for i, t in enumerate(trio):
+        key[tuple(sorted((int(sides.ring[s]), int(sides.plane[s])) for s in t))] = i
+    out = np.empty(len(trio), dtype=np.int64)
+    for i, t in enumerate(trio):
+        out[i] = key[tuple(sorted((int(sides.ring[s]), -int(sides.plane[s])) for s in t))]
+    return out
+
+
+def test_odd_l_weights_flip_between_partners():
+    """Partners (every n negated) have p_z -> -p_z and phi -> pi - phi; by the
+    parity P_l^m(-x) = (-1)^(l+m) P_l^m(x) and cos(m (pi - phi)) = (-1)^m
+    cos(m phi) their weights differ by (-1)^l; the |Y|^2 weights agree."""
+    g = make_geometry(C1_ODD)
+    part = _partner_index(g)
+    sign = np.array([(-1.0) ** l for l, _ in C1_ODD.lms()])
+    assert any(l % 2 for l, _ in C1_ODD.lms())
+    w, d = g.combos.w, g.combos.d
+    assert np.max(np.abs(w[part] - sign * w)) < 1e-13
+    assert np.max(np.abs(d[part] - d)) < 1e-13
+    # and the bins agree (the sorted side lengths are the same)
+    assert np.array_equal(g.combos.bin[part], g.combos.bin)
+
+
+def test_three_plane_waves_odd_l_closed_form():
+    """Odd l of three plane waves: the one bin holds sqrt((2l+1)/4pi) 2 w Im(T)/den
+    with T = V^2 A1 A2 A3 e^{i(phi1+phi2+phi3)} on the combination that carries T."""
+    ng = 16
+    ma, mb = np.array([2, 1, 1]), np.array([-1, 2, -2])
+    mc = -(ma + mb)
+    waves = [(ma, 0.7, 0.3), (mb, 1.1, -1.2), (mc, 0.9, 2.0)]
+    delta = plane_wave_field(ng, waves)
+    g = make_geometry(C1_ODD)
+    T = triple_sums_fft(g, fourier_field(delta))
+    vol = float(ng) ** 3
+    expect = vol ** 2 * 0.7 * 1.1 * 0.9 * np.exp(1j * (0.3 - 1.2 + 2.0))
+    nz = np.flatnonzero(np.abs(T) > 1e-9 * abs(expect))
+    assert len(nz) == 2
+    i = nz[np.argmin(np.abs(T[nz] - expect))]
+    assert abs(T[i] - expect) < 1e-10 * abs(expect)
+    res = multipoles(g, T)
+    c = g.combos
+    lms = C1_ODD.lms()
+    odd = np.array([l % 2 == 1 for l, _ in lms])
+    pref = np.array([math.sqrt((2 * l + 1) / (4 * math.pi)) for l, _ in lms])
+    Bflat = res.B.reshape(len(lms), -1)
+    want = pref * 2 * c.w[i] * np.where(odd, expect.imag, expect.real) / res.den[:, c.bin[i]]
+    assert np.max(np.abs(want[odd])) > 0.05 * np.max(np.abs(want))  # odd l really carry signal
+    assert np.allclose(Bflat[:, c.bin[i]], want, rtol=1e-12, atol=1e-14 * np.max(np.abs(want)))
+
+
+def test_z_reflection_flips_odd_l(c1_field):
+    """delta(x, y, -z): every combination goes to its partner, so even l keep
+    their value and odd l change sign; a z-symmetric field has no odd l."""
+    g = make_geometry(C1_ODD)
+    odd = np.array([l % 2 == 1 for l, _ in C1_ODD.lms()])
+    flip = np.ascontiguousarray(np.roll(c1_field[:, :, ::-1], 1, axis=2))
+    r0 = multipoles(g, triple_sums_fft(g, fourier_field(c1_field)))
+    r1 = multipoles(g, triple_sums_fft(g, fourier_field(flip)))
+    rs = multipoles(g, triple_sums_fft(g, fourier_field(0.5 * (c1_field + flip))))
+    ok = np.isfinite(r0.B)
+    scale = np.nanmax(np.abs(r0.B))
+    B0, B1, Bs = r0.B[ok].reshape(-1), r1.B[ok].reshape(-1), rs.B[ok].reshape(-1)
+    oddm = np.broadcast_to(odd[:, None, None, None], r0.B.shape)[ok].reshape(-1)
+    assert np.max(np.abs(B0[oddm])) > 1e-3 * scale  # odd l are not zero for this field
+    assert np.max(np.abs(B1[~oddm] - B0[~oddm])) < 1e-12 * scale
+    assert np.max(np.abs(B1[oddm] + B0[oddm])) < 1e-12 * scale
+    assert np.max(np.abs(Bs[oddm])) < 1e-12 * scale
+
+
 # --- invariances -------------------------------------------------------------------
 
 
