@@ -106,5 +106,8 @@ def discrete_prediction(geom: Geometry, amp: float, n_s: float, f_ng: float, bet
         np.add.at(num, c.bin, c.w[:, j] * bs * nt)
         np.add.at(den, c.bin, c.d[:, j] * nt)
         ok = den > 0
-        out[j, ok] = math.sqrt((2 * l + 1) / (4.0 * math.pi)) * num[ok] / den[ok]
+        # odd l report the imaginary part of Eq. 13 (the estimator's reading);
+        # the model bispectrum is real, so that part is zero
+        part = np.zeros(nb) if l % 2 else num
+        out[j, ok] = math.sqrt((2 * l + 1) / (4.0 * math.pi)) * part[ok] / den[ok]
     return out.reshape(len(lms), b.n_k1, b.n_mu, b.n_t)
