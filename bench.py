@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile choices")
+    ap.add_argument("--all-l", action="store_true",
+                    help="every l <= 6 (odd l from Im S: twice the contraction's matrix work), not the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
@@ -216,7 +218,9 @@ def main():
         return
     ng = args.ng
     wl = WORKLOADS[ng]
-    binning = bk.make_binning(ng, wl["n_k1"], wl["k1_min"], wl["k1_max"], wl["n_mu"], wl["n_t"])
+    binning = bk.make_binning(ng, wl["n_k1"], wl["k1_min"], wl["k1_max"], wl["n_mu"], wl["n_t"],
+                              even_l_only=0 if args.all_l else 1)
+    n_lm = 28 if args.all_l else 16  # l <= 6, m <= 6: every l, or even l only
     recipe = FieldRecipe(ng, n_s=wl["n_s"], f_ng=0.5, beta=0.5, seed=0)
     delta64 = make_field(recipe)
     digest = field_digest(delta64)
@@ -225,7 +229,7 @@ def main():
 
     ms32, st32, B32, info = time_path(bk, torch, binning, bk.BK_F32, f32, args.steps, args.warmup,
                                       not args.no_autotune)
-    n_values = wl["n_k1"] * wl["n_mu"] * wl["n_t"] * 16
+    n_values = wl["n_k1"] * wl["n_mu"] * wl["n_t"] * n_lm
     out = {
         "metric": METRIC,
         "value": n_values / (ms32 * 1e-3),
@@ -242,10 +246,11 @@ def main():
         "config": {
             "workload": (f"N_g={ng} periodic box (cell 1), field g + 0.5 (g^2 - <g^2>) with P ~ k^{wl['n_s']:g} and Kaiser "
                          f"beta 0.5 along z, seed 0; {wl['n_k1']} linear k1 shells on [1, N_g/3), "
-                         f"{wl['n_mu']} mu x {wl['n_t']} t bins, 16 multipoles l <= 6, m <= 6"),
+                         f"{wl['n_mu']} mu x {wl['n_t']} t bins, {n_lm} multipoles l <= 6, m <= 6"
+                         + (" (every l; odd l from Im S)" if args.all_l else "")),
             "ng": ng,
             "bins": [wl["n_k1"], wl["n_mu"], wl["n_t"]],
-            "n_lm": 16,
+            "n_lm": n_lm,
             "fields_per_step": 1,
             "input": "float32 grid resident in HBM",
         },
@@ -253,9 +258,11 @@ def main():
     stage_names = ["fft3d", "ring_fft", "triple_products", "binning"]
     k3_ms = float(np.mean([s[2] for s in st32]))
     out["stage_ms"] = {k: float(np.mean([s[i] for s in st32])) for i, k in enumerate(stage_names)}
-    flops = info["useful_terms"] * 4.0  # Re(D_A D_C D_B): 2 FMAs per (combination, x_perp) with D_A D_C reused
+    # Re(D_A D_C D_B): 2 FMAs per (combination, x_perp) with D_A D_C reused; Im S (every l) 2 more
+    per_term = 8.0 if args.all_l else 4.0
+    flops = info["useful_terms"] * per_term
     achieved = flops / (k3_ms * 1e-3) / 1e12
-    traffic = read_traffic(ng)
+    traffic = None if args.all_l else read_traffic(ng)
     out["roofline"] = {
         "kernel": "k3_contract_kernel<float>",
         "bound": "mfma",
@@ -265,7 +272,7 @@ def main():
         "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
         "traffic": traffic,
         "algorithmic_flops_per_launch": flops,
-        "dense_flops_per_launch": info["dense_terms"] * 4.0,
+        "dense_flops_per_launch": info["dense_terms"] * per_term,
         "avg_launch_ms": k3_ms,
     }
     out["plan"] = {k: info[k] for k in ("combinations", "work_items", "sides", "rings", "plane_triples")}
@@ -281,7 +288,7 @@ def main():
         }
         out["fp32_vs_fp64_speedup"] = ms64 / ms32
     gold = os.path.join(ROOT, "tests", "golden", f"oracle_ng{ng}.npz")
-    if os.path.exists(gold):
+    if os.path.exists(gold) and not args.all_l:
         g = np.load(gold)
         if str(g["digest"]) == digest:
             ref = g["B"].reshape(16, -1)
@@ -304,7 +311,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": x.numel() * 4, "write": y.numel() * 4}
         del x, y
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.all_l:
         out["cpu_baseline"] = cpu_baseline(delta64, ng, wl, info)
     print(json.dumps(out), flush=True)
 

@@ -76,8 +76,17 @@ typedef struct {
   int n_t;           /* linear t bins on [0.5, 1], top bin closed                          */
   int l_max;         /* <= 12                                                              */
   int m_max;         /* <= l_max                                                           */
-  int even_l_only;   /* must be 1 (odd l vanish for a real field with this weighting)      */
+  int even_l_only;   /* 1: even l only; 0: every l (at most 64 (l, m) outputs), see below  */
 } bk_binning;
+/* Outputs are (l, m) with l = 0..l_max (every l, or even l only) and
+ * m = 0..min(l, m_max).  For a real field a combination of sides and its
+ * partner with every n negated carry conjugate sums S and, with the
+ * mirror-averaged orientation weights, Y weights of equal sign for even l
+ * and opposite sign for odd l.  So the numerator of Eq. 13 is real for even l
+ * and imaginary for odd l.  Each output is the part that does not vanish:
+ * sqrt((2l+1)/4pi) Re(num)/den for even l, sqrt((2l+1)/4pi) Im(num)/den for
+ * odd l (computed from Im S).  Asking for odd l doubles the contraction's
+ * matrix work. */
 
 /* Build the geometry tables (rings, N_tri, combinations, weights, bins) on the
  * host and allocate the device working set on `device` for up to `max_batch`
@@ -189,7 +198,9 @@ typedef struct {
  * B_s at every kept combination's mean-value sides (mu_i = n_i / k_i), binned
  * with exactly the estimator's weights and N_tri (Eq. 13).  Same layout and
  * units as bk_get_multipoles for one field, float64
- * [n_lm][n_k1][n_mu][n_t], NaN where the estimator's bin is empty.  Builds the
+ * [n_lm][n_k1][n_mu][n_t], NaN where the estimator's bin is empty; odd l are
+ * exactly 0 in non-empty bins (the model is the same on a combination and
+ * its n -> -n partner, whose odd-l weights cancel).  Builds the
  * plan geometry on the host (no device needed).  Errors: BK_ERR_ARG for an
  * invalid binning or non-finite model, BK_ERR_SIZE if cap is too small. */
 bk_status bk_discrete_prediction(const bk_binning* binning, const bk_model* model, double* out, size_t cap);

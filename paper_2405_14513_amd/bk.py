@@ -204,7 +204,8 @@ def bk_plan_autotune(plan: int, stream: int = 0) -> list:
 
 
 def bk_discrete_prediction(binning: bk_binning, amp: float, n_s: float, f_ng: float, beta: float) -> np.ndarray:
-    n_lm = sum(min(l, binning.m_max) + 1 for l in range(0, binning.l_max + 1, 2))
+    step = 2 if binning.even_l_only else 1
+    n_lm = sum(min(l, binning.m_max) + 1 for l in range(0, binning.l_max + 1, step))
     shape = (n_lm, binning.n_k1, binning.n_mu, binning.n_t)
     out = np.empty(int(np.prod(shape)), dtype=np.float64)
     model = bk_model(float(amp), float(n_s), float(f_ng), float(beta))

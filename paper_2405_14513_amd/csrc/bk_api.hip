@@ -202,9 +202,16 @@ int pick_tb(int n, size_t elem_bytes) {
 }
 
 #define BK_K3(TT, CHV, TPI, IPW)                                                                                 \
-  hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW>), g3, dim3(bk::kK3Threads), p->lds_k3, st, D,      \
-                     long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides, p->d_S,           \
-                     p->n_items)
+  do {                                                                                                           \
+    if (p->tab.bin.even_l_only)                                                                                  \
+      hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW, false>), g3, dim3(bk::kK3Threads), p->lds_k3, \
+                         st, D, long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides,      \
+                         p->d_S, p->n_items);                                                                    \
+    else                                                                                                         \
+      hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW, true>), g3, dim3(bk::kK3Threads), p->lds_k3,  \
+                         st, D, long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides,      \
+                         p->d_S, p->n_items);                                                                    \
+  } while (0)
 
 // Contraction launch for the plan's item shape (row tiles per item, items per wave).
 template <typename T, int CH>
@@ -299,17 +306,21 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
     dim3 g4(n_bins, B);
     const int nlm = int(p->tab.lm_l.size());
     const long s_per = p->n_items * long(p->item_out);
+    unsigned long long odd_mask = 0;
+    for (int j = 0; j < nlm; ++j)
+      if (p->tab.lm_l[j] % 2) odd_mask |= 1ull << j;
+    const long im_off = long(p->tab.k3.pairs_per_item) * bk::kTileN;  // Im S follows Re S in every item
     if (p->n_chunks > 0) {
       dim3 gp(p->n_chunks, B);
       if (nlm <= 16)
         hipLaunchKernelGGL(bk::k4_partial_kernel<16>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       else if (nlm <= 32)
         hipLaunchKernelGGL(bk::k4_partial_kernel<32>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       else
         hipLaunchKernelGGL(bk::k4_partial_kernel<64>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, p->d_part);
+                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       BK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, p->d_part, p->n_chunks, p->d_bin_chunk, p->d_empty,
@@ -334,7 +345,7 @@ bk_status check_binning(const bk_binning* bn, bk::FftShape* sh, bk::Binning* b) 
   if (bn->k1_max > double(bn->ng) / 3.0) return fail(BK_ERR_ARG, "k1_max must not exceed ng/3");
   if (bn->l_max < 0 || bn->l_max > 12 || bn->m_max < 0 || bn->m_max > bn->l_max)
     return fail(BK_ERR_ARG, "need 0 <= m_max <= l_max <= 12");
-  if (bn->even_l_only != 1) return fail(BK_ERR_ARG, "only even_l_only = 1 is supported");
+  if (bn->even_l_only != 0 && bn->even_l_only != 1) return fail(BK_ERR_ARG, "even_l_only must be 0 or 1");
   if (!(bn->box_len >= 0.0) && !(bn->box_len < 0.0)) return fail(BK_ERR_ARG, "box_len is NaN");
   b->ng = bn->ng;
   b->box_len = bn->box_len > 0 ? bn->box_len : double(bn->ng);
@@ -345,6 +356,9 @@ bk_status check_binning(const bk_binning* bn, bk::FftShape* sh, bk::Binning* b) 
   b->n_t = bn->n_t;
   b->l_max = bn->l_max;
   b->m_max = bn->m_max;
+  b->even_l_only = bn->even_l_only == 1;
+  if (bk::count_lm(b->l_max, b->m_max, b->even_l_only) > 64)
+    return fail(BK_ERR_ARG, "at most 64 multipoles per plan (lower l_max or m_max)");
   return BK_OK;
 }
 
@@ -383,7 +397,7 @@ extern "C" bk_status bk_discrete_prediction(const bk_binning* bn, const bk_model
   bk::Binning b;
   bk_status st = check_binning(bn, &sh, &b);
   if (st != BK_OK) return st;
-  const size_t n_out = size_t(bk::count_lm(b.l_max, b.m_max)) * b.n_k1 * b.n_mu * b.n_t;
+  const size_t n_out = size_t(bk::count_lm(b.l_max, b.m_max, b.even_l_only)) * b.n_k1 * b.n_mu * b.n_t;
   if (cap < n_out) return fail(BK_ERR_SIZE, "output buffer too small");
   bk::Model mdl;
   mdl.amp = model->amp;
@@ -398,6 +412,7 @@ extern "C" bk_status bk_discrete_prediction(const bk_binning* bn, const bk_model
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
   }
   if (!err.empty()) return fail(BK_ERR_ARG, err);
+  if (T.model_pred.size() != n_out) return fail(BK_ERR_ARG, "internal: prediction size mismatch");
   std::copy(T.model_pred.begin(), T.model_pred.end(), out);
   return BK_OK;
 }
@@ -476,7 +491,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   if (p->nkeep > n / 2 + 1) p->nkeep = n / 2 + 1;
   p->n_sides = long(T.side_ring.size());
   p->n_items = long(T.items.size());
-  p->item_out = T.k3.pairs_per_item * bk::kTileN;
+  p->item_out = int(T.s_per_item);
   p->elem = prec == BK_F32 ? 4 : 8;
   const size_t cs = 2 * p->elem;
   // scale so float32 sums stay far from overflow: Delta' = Delta_DFT / N^{3/2}

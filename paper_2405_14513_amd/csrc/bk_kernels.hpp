@@ -284,7 +284,7 @@ struct Unit<double> {
 // tile; float32 units carry two points, i.e. two k-steps.  Float32 partial
 // sums are added to float64 registers every 128 points; float64 accumulates
 // in the MFMA registers.
-template <typename T, int CH, int TPI, int IPW>
+template <typename T, int CH, int TPI, int IPW, bool IMS>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
                                                                  const GroupDesc* __restrict__ groups,
@@ -295,7 +295,8 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   static_assert(G::valid, "the swizzle needs a multiple of 16 units per slot");
   typedef typename Unit<T>::type unit_t;
   constexpr int TILES = TPI * IPW;
-  constexpr int kOut = 16 * TPI * kTileN;  // outputs per item
+  constexpr int kRe = 16 * TPI * kTileN;           // Re S outputs per item
+  constexpr int kOut = kRe * (IMS ? 2 : 1);         // then Im S (odd l requested)
   extern __shared__ char smem_raw[];  // starts at LDS address 0 (no static LDS): 16-byte aligned
   const GroupDesc gd = groups[blockIdx.x];
   const int b = blockIdx.y;
@@ -377,14 +378,22 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   // a float64 wave with one tile keeps the Re and Im products in two
   // accumulators, so consecutive MFMAs do not wait on each other
   constexpr int kChains = sizeof(T) == 8 && TILES == 1 ? 2 : 1;
-  double out[TILES][4];
-  acc_t acc[TILES][kChains];
+  // with IMS, Im S = Re P Im D_B + Im P Re D_B in one more accumulator per tile
+  constexpr int kImT = IMS ? TILES : 1;
+  double out[TILES][4], out_im[kImT][4];
+  acc_t acc[TILES][kChains], acc_im[kImT];
 #pragma unroll
   for (int t = 0; t < TILES; ++t) {
 #pragma unroll
     for (int j = 0; j < kChains; ++j) acc[t][j] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[t][k] = 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < kImT; ++t) {
+    acc_im[t] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out_im[t][k] = 0.0;
   }
 
   for (int c = 0; c < nchunks; ++c) {
@@ -434,6 +443,12 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
           for (int t = 0; t < TILES; ++t)
             acc[t][kChains - 1] = Mfma<T>::step(pn[t], b_c[t / TPI][2 * h + 1], acc[t][kChains - 1]);
+          if constexpr (IMS) {
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) acc_im[t] = Mfma<T>::step(pr[t], b_c[t / TPI][2 * h + 1], acc_im[t]);
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) acc_im[t] = Mfma<T>::step(-pn[t], b_c[t / TPI][2 * h], acc_im[t]);
+          }
         }
       }
       if constexpr (kFlush > 0) {
@@ -443,6 +458,14 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
             for (int k = 0; k < 4; ++k) out[t][k] += double(acc[t][0][k]);
             acc[t][0] = acc_t{0, 0, 0, 0};
+          }
+          if constexpr (IMS) {
+#pragma unroll
+            for (int t = 0; t < TILES; ++t) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) out_im[t][k] += double(acc_im[t][k]);
+              acc_im[t] = acc_t{0, 0, 0, 0};
+            }
           }
         }
       }
@@ -456,6 +479,10 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
         out[t][k] = double(acc[t][0][k]);
         if constexpr (kChains == 2) out[t][k] += double(acc[t][1][k]);
       }
+#pragma unroll
+    for (int t = 0; t < kImT; ++t)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) out_im[t][k] = double(acc_im[t][k]);
   }
 #pragma unroll
   for (int i = 0; i < IPW; ++i) {
@@ -464,7 +491,11 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
 #pragma unroll
     for (int u = 0; u < TPI; ++u)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o[(16 * u + Mfma<T>::out_row(kq, k)) * kTileN + row] = out[TPI * i + u][k];
+      for (int k = 0; k < 4; ++k) {
+        const int cell = (16 * u + Mfma<T>::out_row(kq, k)) * kTileN + row;
+        o[cell] = out[TPI * i + u][k];
+        if constexpr (IMS) o[kRe + cell] = out_im[TPI * i + u][k];
+      }
   }
 }
 
@@ -481,7 +512,7 @@ __global__ __launch_bounds__(64) void mfma_probe_kernel(double* out) {
 }
 
 // ---------------------------------------------------------------- K4
-// Second-level binning in two passes.  The combinations of a bin are
+// Second-level binning in two passes (Re S for even l, Im S for odd l).  The combinations of a bin are
 // contiguous (sorted by output slot) and cut into chunks of at most
 // kK4Chunk.  Pass 1: one wave per (chunk, field); lane l handles multipole
 // j = l % G of combination first + l / G (G = 16, 32 or 64 >= n_lm), so one
@@ -495,6 +526,7 @@ __global__ __launch_bounds__(64) void k4_partial_kernel(const double* __restrict
                                                         const long* __restrict__ chunk_begin,
                                                         const int32_t* __restrict__ combo_slot,
                                                         const double* __restrict__ coef, int n_lm, long n_chunks,
+                                                        unsigned long long odd_mask, long im_off,
                                                         double* __restrict__ part) {
   constexpr int per_iter = 64 / G;
   const long ch = blockIdx.x;
@@ -502,7 +534,8 @@ __global__ __launch_bounds__(64) void k4_partial_kernel(const double* __restrict
   const int lane = threadIdx.x;
   const int j = lane % G, cc = lane / G;
   const long c0 = chunk_begin[ch], c1 = chunk_begin[ch + 1];
-  const double* Sb = S + size_t(b) * s_per_batch;
+  // odd l (bit j of odd_mask) take Im S, stored im_off after Re S
+  const double* Sb = S + size_t(b) * s_per_batch + ((odd_mask >> j) & 1ull ? im_off : 0);
   double acc = 0.0;
   if (j < n_lm) {
 #pragma unroll 4

@@ -53,9 +53,9 @@ struct Candidate {
 
 }  // namespace
 
-int count_lm(int l_max, int m_max) {
+int count_lm(int l_max, int m_max, bool even_only) {
   int n = 0;
-  for (int l = 0; l <= l_max; l += 2) n += std::min(l, m_max) + 1;
+  for (int l = 0; l <= l_max; l += even_only ? 2 : 1) n += std::min(l, m_max) + 1;
   return n;
 }
 
@@ -70,6 +70,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   const int ipw = k3.items_per_wave;
   if (ipw != 1 && !(ipw == 2 && ppi == 16)) return "items per wave must be 1, or 2 with 16 pairs per item";
   if (k3.max_group_sides < 1 || k3.max_group_sides > kMaxGroupSidesLimit) return "staged sides per workgroup out of range";
+  T.s_per_item = int64_t(ppi) * kTileN * (b.even_l_only ? 1 : 2);
   const int ng = b.ng;
   T.ng = ng;
   if (n_threads < 1) n_threads = 1;
@@ -202,13 +203,17 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     return T.side_of[size_t(n_abs) * (nr + 1) + r];
   };
 
-  // ---- outputs
-  for (int l = 0; l <= b.l_max; l += 2)
+  // ---- outputs.  For odd l a combination and its n -> -n partner carry
+  // conjugate S and weights of opposite sign, so their sum is 2 i w Im S: odd
+  // l are reported as the imaginary part of Eq. 13 (real part zero), and the
+  // same coefficient multiplies Im S instead of Re S.
+  for (int l = 0; l <= b.l_max; l += b.even_l_only ? 2 : 1)
     for (int m = 0; m <= std::min(l, b.m_max); ++m) {
       T.lm_l.push_back(l);
       T.lm_m.push_back(m);
     }
   const int nlm = int(T.lm_l.size());
+  if (nlm > 64) return "at most 64 multipoles per plan";
   std::vector<double> nlm_norm(nlm), pref(nlm);
   for (int j = 0; j < nlm; ++j) {
     nlm_norm[j] = norm_lm(T.lm_l[j], T.lm_m[j]);
@@ -367,7 +372,9 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
       mean_w[cr.bin] += wgt;
       if (model)
         for (int j = 0; j < nlm; ++j)
-          model_num[size_t(j) * n_bins + cr.bin] += wgt * per_pt_w[ip][i * nlm + j] * per_pt_model[ip][i];
+          // the model is the same on both partners, whose odd-l weights cancel
+          if (T.lm_l[j] % 2 == 0)
+            model_num[size_t(j) * n_bins + cr.bin] += wgt * per_pt_w[ip][i * nlm + j] * per_pt_model[ip][i];
       if (cr.mult == 1) T.n_self_partner += 1;
       ++total;
     }
@@ -595,7 +602,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
         auto& slot_of = pt_combo_slot[it.pt];
         for (int p = 0; p < int(it.segs.size()); ++p)
           for (int ci : segs[it.segs[p]].idx)
-            slot_of[ci] = item_index * (ppi * kTileN) + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
+            slot_of[ci] = item_index * T.s_per_item + int64_t(p) * kTileN + (recs[ci].rb - it.lo);
         T.items.push_back(d);
         T.dense_terms += double(ppi) * kTileN * double(m) * double(m);
       }

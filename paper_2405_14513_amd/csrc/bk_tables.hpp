@@ -28,6 +28,7 @@ struct Binning {
   double k1_min = 0.0, k1_max = 0.0;
   int n_mu = 0, n_t = 0;
   int l_max = 6, m_max = 6;
+  bool even_l_only = true;  // false: odd l too, as the imaginary part (see build_tables)
 };
 
 // Sizes of the K3 work decomposition.
@@ -113,6 +114,9 @@ struct Tables {
   std::vector<int32_t> group_sides;      // per LDS slot: grid-side index | swizzle key << kKeyShift
   int max_group_sides = 0;
   double dense_terms = 0.0, useful_terms = 0.0;
+  // float64 outputs of the contraction per work item: Re S of every (pair,
+  // column) cell, followed by Im S when odd l are requested
+  int64_t s_per_item = 0;
 };
 
 // The paper's model field (Eqs. 14-17): P(k) = amp k^n_s with k in units of
@@ -133,7 +137,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
 // parts vanish for this model (mirror symmetry in p_y).
 std::vector<double> continuum_multipoles(int l_max, int m_max, double mu, double t, double beta);
 
-// Number of (l, m) outputs for l_max, m_max (even l only).
-int count_lm(int l_max, int m_max);
+// Number of (l, m) outputs for l_max, m_max (even l only, or every l).
+int count_lm(int l_max, int m_max, bool even_only = true);
 
 }  // namespace bk

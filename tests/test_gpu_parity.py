@@ -49,20 +49,20 @@ def per_multipole_error(B, ref):
 _ORACLE_CACHE = {}
 
 
-def oracle_result(args, recipe):
-    key = (args, recipe)
+def oracle_result(args, recipe, even=True):
+    key = (args, recipe, even)
     if key not in _ORACLE_CACHE:
-        b = Binning(*args[:6], box_len=args[6] if len(args) > 6 else None)
+        b = Binning(*args[:6], box_len=args[6] if len(args) > 6 else None, even_l_only=even)
         delta = make_field(recipe)
         _ORACLE_CACHE[key] = (b, delta, estimate(delta, b))
     return _ORACLE_CACHE[key]
 
 
-def run_gpu(args, delta, prec, batch_fields=None, as_f32=False, device_input=True):
+def run_gpu(args, delta, prec, batch_fields=None, as_f32=False, device_input=True, even=True):
     torch = _torch()
     from paper_2405_14513_amd import bk
 
-    binning = bk.make_binning(*args[:6], box_len=args[6] if len(args) > 6 else 0.0)
+    binning = bk.make_binning(*args[:6], box_len=args[6] if len(args) > 6 else 0.0, even_l_only=int(even))
     fields = [delta] if batch_fields is None else batch_fields
     arr = np.stack(fields).astype(np.float32 if as_f32 else np.float64)
     est = bk.Estimator(binning, prec=prec, max_batch=len(fields))
@@ -106,6 +106,21 @@ def test_parity_against_oracle(case, prec):
     assert err.max() < TOL[prec], err
 
 
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("case", [0, 1, 2, 4], ids=[f"ng{CASES[i][0][0]}" for i in (0, 1, 2, 4)])
+def test_odd_l_parity(case, prec):
+    """All l up to 6 (odd l from Im S, the imaginary part of Eq. 13) against the oracle."""
+    args, recipe = CASES[case]
+    _say(f"odd-l parity ng={args[0]} prec={prec}")
+    b, delta, ref = oracle_result(args, recipe, even=False)
+    B, counts, lms = run_gpu(args, delta, prec, even=False)
+    assert lms == b.lms() and any(l % 2 for l, _ in lms)
+    assert np.array_equal(counts, ref.counts)
+    err = per_multipole_error(B[0], ref.B)
+    _say(f"  max error per multipole {err.max():.3e}")
+    assert err.max() < TOL[prec], err
+
+
 WORK_SHAPES = {"items1": {"BK_K3_ITEMS": "1"}, "pairs32": {"BK_K3_PAIRS": "32"},
                "pairs64": {"BK_K3_PAIRS": "64"}, "sides48": {"BK_K3_SIDES": "48"}}
 
@@ -118,11 +133,12 @@ def test_other_work_item_shapes(shape, prec, monkeypatch):
     and a small staged-side cap (many workgroups of few items); the default is
     two 16-pair items per wave."""
     args, recipe = CASES[3]
-    _say(f"work item shape {shape}, ng={args[0]} prec={prec}")
-    b, delta, ref = oracle_result(args, recipe)
+    even = shape != "pairs32"  # one shape also takes the Im S path (odd l)
+    _say(f"work item shape {shape}, ng={args[0]} prec={prec} even_l_only={even}")
+    b, delta, ref = oracle_result(args, recipe, even=even)
     for k, v in WORK_SHAPES[shape].items():
         monkeypatch.setenv(k, v)
-    B, counts, lms = run_gpu(args, delta, prec)
+    B, counts, lms = run_gpu(args, delta, prec, even=even)
     assert np.array_equal(counts, ref.counts)
     err = per_multipole_error(B[0], ref.B)
     _say(f"  max error per multipole {err.max():.3e}")

@@ -22,11 +22,13 @@ from paper_2405_14513_amd import bk
         ((16, 3, 2.0, 5.0, 5, 3, 0.0), (1.3, -2.0, 0.25, 0.0)),
     ],
 )
-def test_discrete_prediction_matches_oracle(args, model):
+@pytest.mark.parametrize("even", [True, False], ids=["even_l", "all_l"])
+def test_discrete_prediction_matches_oracle(args, model, even):
     ng, n_k1, k1_min, k1_max, n_mu, n_t, box = args
-    b = Binning(ng, n_k1, k1_min, k1_max, n_mu, n_t, box_len=box if box > 0 else None)
+    b = Binning(ng, n_k1, k1_min, k1_max, n_mu, n_t, box_len=box if box > 0 else None, even_l_only=even)
     ref = discrete_prediction(make_geometry(b), *model)
-    got = bk.bk_discrete_prediction(bk.make_binning(ng, n_k1, k1_min, k1_max, n_mu, n_t, box_len=box), *model)
+    got = bk.bk_discrete_prediction(bk.make_binning(ng, n_k1, k1_min, k1_max, n_mu, n_t, box_len=box,
+                                                    even_l_only=int(even)), *model)
     assert got.shape == ref.shape
     assert np.array_equal(np.isnan(got), np.isnan(ref))
     ok = ~np.isnan(ref)
