@@ -285,10 +285,32 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
       // columns per block: 8 (float32) or 4 (float64) by default, i.e. 64-byte row segments
       const int tb2 = fit_tb(m, p->k2_tb > 0 ? p->k2_tb : (prec_is_f32<T>() ? 8 : 4), cs);
       dim3 g2(n_gs * (m / tb2), B);
-      hipLaunchKernelGGL((bk::k2_fused_kernel<T>), g2, dim3(256), fft_lds_bytes(m, tb2, cs), st, F, D, p->d_gs_side,
-                         p->d_gs_off, lvb[L], long(p->tab.d_elems), p->d_side_ring, p->d_side_plane, p->d_side_u,
-                         p->d_ring_seg_off, p->d_ring_seg, p->d_ring_mode_uy, n, p->nkeep, twl + p->tw_lv_off[L],
-                         p->lv_sh[L], tb2);
+      const size_t lds2 = fft_lds_bytes(m, tb2, cs);
+      // one instance per grid size the tables can produce; any other size takes the runtime-length kernel
+#define BK_K2(MV)                                                                                                \
+  hipLaunchKernelGGL((bk::k2_fused_kernel<T, MV>), g2, dim3(256), lds2, st, F, D, p->d_gs_side, p->d_gs_off,     \
+                     lvb[L], long(p->tab.d_elems), p->d_side_ring, p->d_side_plane, p->d_side_u, p->d_ring_seg_off, \
+                     p->d_ring_seg, p->d_ring_mode_uy, n, p->nkeep, twl + p->tw_lv_off[L], p->lv_sh[L], tb2)
+      switch (m) {
+        case 8: BK_K2(8); break;
+        case 16: BK_K2(16); break;
+        case 24: BK_K2(24); break;
+        case 32: BK_K2(32); break;
+        case 40: BK_K2(40); break;
+        case 48: BK_K2(48); break;
+        case 64: BK_K2(64); break;
+        case 80: BK_K2(80); break;
+        case 96: BK_K2(96); break;
+        case 128: BK_K2(128); break;
+        case 160: BK_K2(160); break;
+        case 192: BK_K2(192); break;
+        case 256: BK_K2(256); break;
+        case 320: BK_K2(320); break;
+        case 384: BK_K2(384); break;
+        case 512: BK_K2(512); break;
+        default: BK_K2(0);
+      }
+#undef BK_K2
       BK_HIP(hipGetLastError());
     }
   }

@@ -36,6 +36,49 @@ struct FftShape {
   int radix[12];
 };
 
+// In-register radix-R DFT of v[0..R-1] (forward sign).
+template <typename T, int R>
+__device__ __forceinline__ void butterfly(cplx<T> (&v)[R]) {
+  if constexpr (R == 2) {
+    const cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
+    const T h = T(0.5);
+    const T s3 = T(0.86602540378443864676);
+    const cplx<T> t1 = cadd(v[1], v[2]);
+    const cplx<T> t2 = {v[0].x - h * t1.x, v[0].y - h * t1.y};
+    const cplx<T> t3 = {s3 * (v[1].y - v[2].y), -s3 * (v[1].x - v[2].x)};  // -i sqrt3/2 (v1 - v2)
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  } else if constexpr (R == 5) {
+    // y_k = sum_j v_j w^{jk}, w = e^{-2 pi i / 5}: pair j with 5 - j
+    const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+    const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+    const cplx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const cplx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const cplx<T> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    const cplx<T> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    const cplx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    const cplx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = {a1.x + b1.y, a1.y - b1.x};  // a1 - i b1
+    v[4] = {a1.x - b1.y, a1.y + b1.x};  // a1 + i b1
+    v[2] = {a2.x + b2.y, a2.y - b2.x};
+    v[3] = {a2.x - b2.y, a2.y + b2.x};
+  } else if constexpr (R == 4) {
+    const cplx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const cplx<T> b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    const cplx<T> mib1 = {b1.y, -b1.x};  // -i * b1
+    v[0] = cadd(a0, b0);
+    v[1] = cadd(a1, mib1);
+    v[2] = csub(a0, b0);
+    v[3] = csub(a1, mib1);
+  }
+}
+
 // One Stockham pass over `lines` transforms held in LDS, src -> dst.
 // Element i of line l lives at buf[l * ls + i].
 template <typename T, int R>
@@ -56,47 +99,64 @@ __device__ __forceinline__ void stockham_pass(const cplx<T>* __restrict__ src, c
 #pragma unroll
       for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(k * r * tw_step) % n]);
     }
-    if constexpr (R == 2) {
-      const cplx<T> a = v[0], b = v[1];
-      v[0] = cadd(a, b);
-      v[1] = csub(a, b);
-    } else if constexpr (R == 3) {
-      // e^{-2 pi i / 3} = -1/2 - i sqrt(3)/2
-      const T h = T(0.5);
-      const T s3 = T(0.86602540378443864676);
-      const cplx<T> t1 = cadd(v[1], v[2]);
-      const cplx<T> t2 = {v[0].x - h * t1.x, v[0].y - h * t1.y};
-      const cplx<T> t3 = {s3 * (v[1].y - v[2].y), -s3 * (v[1].x - v[2].x)};  // -i sqrt3/2 (v1 - v2)
-      v[0] = cadd(v[0], t1);
-      v[1] = cadd(t2, t3);
-      v[2] = csub(t2, t3);
-    } else if constexpr (R == 5) {
-      // y_k = sum_j v_j w^{jk}, w = e^{-2 pi i / 5}: pair j with 5 - j
-      const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
-      const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
-      const cplx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-      const cplx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-      const cplx<T> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
-      const cplx<T> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
-      const cplx<T> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
-      const cplx<T> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
-      v[0] = cadd(v[0], cadd(t1, t2));
-      v[1] = {a1.x + b1.y, a1.y - b1.x};  // a1 - i b1
-      v[4] = {a1.x - b1.y, a1.y + b1.x};  // a1 + i b1
-      v[2] = {a2.x + b2.y, a2.y - b2.x};
-      v[3] = {a2.x - b2.y, a2.y + b2.x};
-    } else if constexpr (R == 4) {
-      const cplx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
-      const cplx<T> b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
-      const cplx<T> mib1 = {b1.y, -b1.x};  // -i * b1
-      v[0] = cadd(a0, b0);
-      v[1] = cadd(a1, mib1);
-      v[2] = csub(a0, b0);
-      v[3] = csub(a1, mib1);
-    }
+    butterfly<T, R>(v);
     cplx<T>* d = dst + l * ls + (j / ns) * ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) d[r * ns] = v[r];
+  }
+}
+
+// The same pass with the length N and the stride NS known at compile time:
+// the index arithmetic becomes shifts and constant multiplies, and the
+// twiddle index k r (N / (NS R)) < N needs no reduction.
+template <typename T, int R, int N, int NS>
+__device__ __forceinline__ void stockham_pass_c(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
+                                                const cplx<T>* __restrict__ tw, int lines, int ls) {
+  constexpr int nb = N / R;
+  constexpr int tw_step = N / (NS * R);
+  const int total = lines * nb;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int l = q / nb;
+    const int j = q - l * nb;
+    const int k = j % NS;
+    const cplx<T>* s = src + l * ls;
+    cplx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tw_step]);
+    }
+    butterfly<T, R>(v);
+    cplx<T>* d = dst + l * ls + (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[r * NS] = v[r];
+  }
+}
+
+// Radix sequence of a compile-time length N = 2^a 3^b 5^c: radix 4 while it
+// divides the power of two, one radix 2 if a is odd, then 3s, then 5s (the
+// order of fft_shape on the host).
+template <int N>
+struct Radices {
+  static constexpr int pw(int n, int p) { return n % p == 0 ? 1 + pw(n / p, p) : 0; }
+  static constexpr int p2 = pw(N, 2), p3 = pw(N, 3), p5 = pw(N, 5);
+  static constexpr int n4 = p2 / 2, n2 = p2 % 2;
+  static constexpr int count = n4 + n2 + p3 + p5;
+  static constexpr int radix(int s) { return s < n4 ? 4 : s < n4 + n2 ? 2 : s < n4 + n2 + p3 ? 3 : 5; }
+};
+
+// Passes S.. of a compile-time-length transform, stride NS so far; returns
+// the buffer holding the result.
+template <typename T, int N, int S = 0, int NS = 1>
+__device__ cplx<T>* lds_fft_c(cplx<T>* src, cplx<T>* dst, const cplx<T>* tw, int lines, int ls) {
+  if constexpr (S == Radices<N>::count) {
+    return src;
+  } else {
+    constexpr int R = Radices<N>::radix(S);
+    stockham_pass_c<T, R, N, NS>(src, dst, tw, lines, ls);
+    __syncthreads();
+    return lds_fft_c<T, N, S + 1, NS * R>(dst, src, tw, lines, ls);
   }
 }
 

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
 // ring reaching this level has 2 U < m, so no two modes share a position.
 // ring_mode_uy holds each ring's modes sorted by (u_x, u_y); ring_seg gives,
 // per ring, the start of every row u_x = -U..U (2U + 2 offsets from ring_seg_off[r]).
-template <typename T>
+template <typename T, int M>
 __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ D,
                                                        const int32_t* __restrict__ gside_side,
                                                        const int64_t* __restrict__ gside_off, int gs_begin,
@@ -127,15 +127,18 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
                                                        const int16_t* __restrict__ ring_mode_uy, int ng, int nkeep,
                                                        const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
-  const int m = sh.n;
+  // M > 0: the grid size is the compile-time M (sh.n == M) and the FFT's
+  // index arithmetic folds to constants; M = 0: any size, from sh
+  const int m = M > 0 ? M : sh.n;
   const int ls = m + 1;
+  const int tb_shift = __builtin_ctz(unsigned(tb));  // tb is a power of two
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw_l + m;
   cplx<T>* b1 = b0 + tb * ls;
   for (int i = threadIdx.x; i < m; i += blockDim.x) tw_l[i] = tw[i];
-  const int ytiles = m / tb;
+  const int ytiles = m >> tb_shift;
   const int gs = gs_begin + int(blockIdx.x) / ytiles;
-  const int y0 = (blockIdx.x % ytiles) * tb;
+  const int y0 = (int(blockIdx.x) - (gs - gs_begin) * ytiles) << tb_shift;
   const int b = blockIdx.y;
   const int s = gside_side[gs];
   const int r = side_ring[s];
@@ -155,9 +158,10 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
   };
   // one item = one row u_x and the two columns y0 + l, y0 + l + tb / 2
   // (one column when tb = 1)
-  const int half = tb > 1 ? tb / 2 : 1;
+  const int half_shift = tb > 1 ? tb_shift - 1 : 0;
+  const int half = 1 << half_shift;
   for (int q = threadIdx.x; q < nrow * half; q += blockDim.x) {
-    const int row = q / half, l = q - row * half;
+    const int row = q >> half_shift, l = q & (half - 1);
     const int ux = row - U;
     const int nc = tb > 1 ? 2 : 1;
     int yc[2] = {y0 + l, y0 + l + half};
@@ -204,10 +208,14 @@ __global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict
     for (int c = 0; c < nc; ++c) b0[(l + c * half) * ls + pos] = acc[c];
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
+  cplx<T>* res;
+  if constexpr (M > 0)
+    res = lds_fft_c<T, M>(b0, b1, tw_l, tb, ls);
+  else
+    res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   cplx<T>* Ds = D + size_t(b) * d_elems + gside_off[gs];
   for (int q = threadIdx.x; q < tb * m; q += blockDim.x) {
-    const int x = q / tb, l = q - x * tb;
+    const int x = q >> tb_shift, l = q & (tb - 1);
     Ds[size_t(x) * m + y0 + l] = res[l * ls + x];
   }
 }
