@@ -107,7 +107,7 @@ struct bk_plan_s {
   double* d_part = nullptr;       // K4 partial sums [max_batch][n_chunks][n_lm]
   long n_chunks = 0;
   int32_t* d_combo_slot = nullptr;
-  double* d_coef = nullptr;
+  void* d_coef = nullptr;         // per-combination coefficients, float32 (BK_F32 plans) or float64
   unsigned char* d_empty = nullptr;
   hipEvent_t ev[5] = {};
   bool have_events = false;
@@ -335,14 +335,14 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
     if (p->n_chunks > 0) {
       dim3 gp(p->n_chunks, B);
       if (nlm <= 16)
-        hipLaunchKernelGGL(bk::k4_partial_kernel<16>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<16, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       else if (nlm <= 32)
-        hipLaunchKernelGGL(bk::k4_partial_kernel<32>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<32, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       else
-        hipLaunchKernelGGL(bk::k4_partial_kernel<64>, gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, p->d_coef, nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<64, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
       BK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, p->d_part, p->n_chunks, p->d_bin_chunk, p->d_empty,
@@ -646,7 +646,15 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   }
   TRY(put(p, &p->d_bin_ptr, bin_ptr.data(), bin_ptr.size()));
   TRY(put(p, &p->d_combo_slot, cslot.data(), cslot.size()));
-  TRY(put(p, &p->d_coef, T.combo_coef.data(), T.combo_coef.size()));
+  // Coefficients in the plan's precision: float32 rounding (2^-24 relative)
+  // of each coefficient is far below the float32 path's error, and halves
+  // the bytes the binning reads; the per-bin sums stay float64.
+  if (prec == BK_F32) {
+    std::vector<float> c32(T.combo_coef.begin(), T.combo_coef.end());
+    TRY(put(p, reinterpret_cast<float**>(&p->d_coef), c32.data(), c32.size()));
+  } else {
+    TRY(put(p, reinterpret_cast<double**>(&p->d_coef), T.combo_coef.data(), T.combo_coef.size()));
+  }
   TRY(put(p, &p->d_empty, T.bin_empty_lm.data(), T.bin_empty_lm.size()));
 #undef TRY
   // the host copies of the per-combination arrays are no longer needed

@@ -529,11 +529,11 @@ __global__ __launch_bounds__(64) void mfma_probe_kernel(double* out) {
 // the chunk partials are added in chunk order and scaled; empty bins are NaN.
 constexpr int kK4Chunk = 1024;
 
-template <int G>
+template <int G, typename CT>
 __global__ __launch_bounds__(64) void k4_partial_kernel(const double* __restrict__ S, long s_per_batch,
                                                         const long* __restrict__ chunk_begin,
                                                         const int32_t* __restrict__ combo_slot,
-                                                        const double* __restrict__ coef, int n_lm, long n_chunks,
+                                                        const CT* __restrict__ coef, int n_lm, long n_chunks,
                                                         unsigned long long odd_mask, long im_off,
                                                         double* __restrict__ part) {
   constexpr int per_iter = 64 / G;
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(64) void k4_partial_kernel(const double* __restrict
   double acc = 0.0;
   if (j < n_lm) {
 #pragma unroll 4
-    for (long c = c0 + cc; c < c1; c += per_iter) acc += coef[size_t(c) * n_lm + j] * Sb[combo_slot[c]];
+    for (long c = c0 + cc; c < c1; c += per_iter) acc += double(coef[size_t(c) * n_lm + j]) * Sb[combo_slot[c]];
   }
 #pragma unroll
   for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
