@@ -57,3 +57,57 @@ def test_fullsize_against_stored_oracle(ng, prec):
     print(f"  max error per multipole {err.max():.3e}", flush=True)
     # float32: input rounded to float32, float32 FFTs and products, float64 sums
     assert err.max() < (1e-11 if prec == 2 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("ng", [128, 256])
+def test_fullsize_every_l(ng, prec):
+    """Every l at full size: the even l of an every-l plan equal the stored
+    even-l oracle values, and under a z reflection of the field the odd l
+    (Im S) change sign while the even l stay, as they must (the reflection maps
+    every combination to its n -> -n partner)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_14513_amd import bk
+
+    print(f"full-size every-l ng={ng} prec={prec}", flush=True)
+    gold = np.load(os.path.join(HERE, "golden", f"oracle_ng{ng}.npz"))
+    delta = make_field(FieldRecipe(ng, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0))
+    assert field_digest(delta) == str(gold["digest"]), "regenerated field differs from the stored one"
+    flip = np.ascontiguousarray(np.roll(delta[:, :, ::-1], 1, axis=2))
+    est = bk.Estimator(bk.make_binning(ng, *WORKLOADS[ng], even_l_only=0), prec=prec)
+    out = []
+    try:
+        s = torch.cuda.current_stream().cuda_stream
+        for field in (delta, flip):
+            t = torch.from_numpy(field.astype(np.float32) if prec == 1 else field).cuda()
+            est.load(t, s)
+            est.estimate(s)
+            out.append(est.multipoles()[0])
+        lms = est.lm_list()
+        counts = est.counts()
+    finally:
+        est.close()
+    tol = 1e-11 if prec == 2 else 1e-5
+    assert np.array_equal(counts, gold["counts"])
+    even = [j for j, (l, _) in enumerate(lms) if l % 2 == 0]
+    odd = [j for j, (l, _) in enumerate(lms) if l % 2 == 1]
+    assert [lms[j] for j in even] == [tuple(x) for x in gold["lms"].tolist()]
+    B, Bf = out[0].reshape(len(lms), -1), out[1].reshape(len(lms), -1)
+    ref = gold["B"].reshape(len(even), -1)
+    ok = ~np.isnan(ref)
+    for i, j in enumerate(even):
+        scale = np.max(np.abs(ref[i][ok[i]]))
+        assert np.max(np.abs(B[j][ok[i]] - ref[i][ok[i]])) < tol * scale, lms[j]
+        assert np.max(np.abs(Bf[j][ok[i]] - ref[i][ok[i]])) < tol * scale, lms[j]
+    mono = np.max(np.abs(ref[0][ok[0]]))
+    worst = 0.0
+    for j in odd:
+        okj = ~np.isnan(B[j])
+        scale = np.max(np.abs(B[j][okj]))
+        assert scale > 1e-6 * mono, lms[j]  # odd l carry signal in a finite realisation
+        worst = max(worst, np.max(np.abs(Bf[j][okj] + B[j][okj])) / scale)
+    print(f"  odd-l reflection residual {worst:.3e}", flush=True)
+    assert worst < tol
