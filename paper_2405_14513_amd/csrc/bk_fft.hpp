@@ -2,10 +2,11 @@
 //
 // All transforms here are forward DFTs, y[k] = sum_j x[j] e^{-2 pi i j k / N}:
 // the 3-D transform of the field (Sec. II) and the ring sums of Eq. 9, whose
-// exponent carries the same minus sign.  N = 2^a 3^b 5^c with b, c <= 1;
-// stages use radix 4, then one radix 2 if a is odd, then one radix 3 and one
-// radix 5.  Twiddles are a table exp(-2 pi i t / N), t < N, computed on the
-// host in float64 and cast.
+// exponent carries the same minus sign.  N = 2^a 3^b 5^c; stages use radix
+// 4, then one radix 2 if a is odd, then radix 3 and radix 5 (the runtime-
+// length lds_fft takes b, c <= 1, as the host's fft_shape; lds_fft_c has N
+// and every stage's stride as compile-time constants).  Twiddles are a table
+// exp(-2 pi i t / N), t < N, computed on the host in float64 and cast.
 #pragma once
 
 #include <hip/hip_runtime.h>

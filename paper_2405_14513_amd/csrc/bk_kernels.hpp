@@ -283,15 +283,16 @@ struct Unit<double> {
 // One block = one GroupDesc (items on one grid of m x m points that share
 // the sides staged in LDS); wave w contracts items IPW w .. IPW w + IPW - 1,
 // each 16 TPI ring pairs x 16 slot-B rings (TPI row tiles sharing the slot-B
-// reads), TILES = TPI IPW row tiles in all.  The m^2 points are visited in chunks of CH: while the
-// waves contract chunk c from one LDS buffer, the direct loads of chunk c+1
-// fill the other.  Per 16-byte unit step, lane (row, kq) reads unit 4 q + kq
-// of its pair's A and C slots and of its column's B slot, forms the pair
-// products P = D_A conj(D_C) and feeds Re P, -Im P against Re D_B, Im D_B into
-// 16x16x4 MFMAs (K = the 4 points of the lanes' kq), one accumulator per row
-// tile; float32 units carry two points, i.e. two k-steps.  Float32 partial
-// sums are added to float64 registers every 128 points; float64 accumulates
-// in the MFMA registers.
+// reads), TILES = TPI IPW row tiles in all.  The m^2 points are visited in
+// chunks of CH: while the waves contract chunk c from one LDS buffer, the
+// direct loads of chunk c+1 fill the other.  Per 16-byte unit step, lane
+// (row, kq) reads unit 4 q + kq of its pair's A and C slots and of its
+// column's B slot, forms the pair products P = D_A conj(D_C) and feeds
+// Re P, -Im P against Re D_B, Im D_B into 16x16x4 MFMAs (K = the 4 points of
+// the lanes' kq), one accumulator per row tile (Re S; with IMS a second one
+// takes Re P Im D_B + Im P Re D_B = Im S); float32 units carry two points,
+// i.e. two k-steps.  Float32 partial sums are added to float64 registers
+// every 128 points; float64 accumulates in the MFMA registers.
 template <typename T, int CH, int TPI, int IPW, bool IMS>
 __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
