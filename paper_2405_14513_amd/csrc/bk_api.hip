@@ -243,6 +243,24 @@ void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
 }
 #undef BK_K3
 
+// The three K1 passes for a transform length N known at compile time (0: any).
+template <typename T, int N>
+void launch_k1(bk_plan p, bk::cplx<T>* F, const bk::cplx<T>* tw, int tb, size_t lds, hipStream_t st) {
+  const int n = p->sh.n;
+  const int B = p->batch;
+  dim3 grid(n * (n / tb), B);
+  if (p->in_dtype == BK_F32)
+    hipLaunchKernelGGL((bk::k1_z_kernel<T, float, N>), grid, dim3(256), lds, st,
+                       reinterpret_cast<const float*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+  else
+    hipLaunchKernelGGL((bk::k1_z_kernel<T, double, N>), grid, dim3(256), lds, st,
+                       reinterpret_cast<const double*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+  const long lines = long(B) * p->nkeep * n;
+  hipLaunchKernelGGL((bk::k_rows_kernel<T, N>), dim3((lines + tb - 1) / tb), dim3(256), lds, st, F, tw, p->sh, tb,
+                     lines);
+  hipLaunchKernelGGL((bk::k_cols_kernel<T, N>), dim3(n / tb, B * p->nkeep), dim3(256), lds, st, F, tw, p->sh, tb);
+}
+
 template <typename T>
 bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   using C = bk::cplx<T>;
@@ -256,23 +274,23 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
   C* D = reinterpret_cast<C*>(p->d_D);
 
   if (timing) BK_HIP(hipEventRecord(p->ev[0], st));
-  // K1: z pass (real input), y rows, x columns
-  {
-    dim3 grid(n * (n / tb), B);
-    if (p->in_dtype == BK_F32)
-      hipLaunchKernelGGL((bk::k1_z_kernel<T, float>), grid, dim3(256), lds_fft, st,
-                         reinterpret_cast<const float*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
-    else
-      hipLaunchKernelGGL((bk::k1_z_kernel<T, double>), grid, dim3(256), lds_fft, st,
-                         reinterpret_cast<const double*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
-    BK_HIP(hipGetLastError());
-    const long lines = long(B) * p->nkeep * n;
-    hipLaunchKernelGGL((bk::k_rows_kernel<T>), dim3((lines + tb - 1) / tb), dim3(256), lds_fft, st, F, tw, p->sh,
-                       tb, lines);
-    BK_HIP(hipGetLastError());
-    hipLaunchKernelGGL((bk::k_cols_kernel<T>), dim3(n / tb, B * p->nkeep), dim3(256), lds_fft, st, F, tw, p->sh, tb);
-    BK_HIP(hipGetLastError());
+  // K1: z pass (real input), y rows, x columns; one instance per supported N_g
+  switch (n) {
+    case 8: launch_k1<T, 8>(p, F, tw, tb, lds_fft, st); break;
+    case 16: launch_k1<T, 16>(p, F, tw, tb, lds_fft, st); break;
+    case 24: launch_k1<T, 24>(p, F, tw, tb, lds_fft, st); break;
+    case 32: launch_k1<T, 32>(p, F, tw, tb, lds_fft, st); break;
+    case 48: launch_k1<T, 48>(p, F, tw, tb, lds_fft, st); break;
+    case 64: launch_k1<T, 64>(p, F, tw, tb, lds_fft, st); break;
+    case 96: launch_k1<T, 96>(p, F, tw, tb, lds_fft, st); break;
+    case 128: launch_k1<T, 128>(p, F, tw, tb, lds_fft, st); break;
+    case 192: launch_k1<T, 192>(p, F, tw, tb, lds_fft, st); break;
+    case 256: launch_k1<T, 256>(p, F, tw, tb, lds_fft, st); break;
+    case 384: launch_k1<T, 384>(p, F, tw, tb, lds_fft, st); break;
+    case 512: launch_k1<T, 512>(p, F, tw, tb, lds_fft, st); break;
+    default: launch_k1<T, 0>(p, F, tw, tb, lds_fft, st);
   }
+  BK_HIP(hipGetLastError());
   if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
   // K2: ring sums, pruned row DFT + column FFT per (grid side, column block), one launch per grid level
   {

@@ -22,13 +22,15 @@ namespace bk {
 
 // ---------------------------------------------------------------- K1
 // z pass: real input lines delta[b][x][y][:] (contiguous), `tb` consecutive y
-// per block; writes F[b][n][x][y] for n < nkeep, scaled by `scale`.
-template <typename T, typename Tin>
+// per block; writes F[b][n][x][y] for n < nkeep, scaled by `scale`.  The K1
+// kernels take the length N at compile time (N = sh.n) or at run time (N = 0).
+template <typename T, typename Tin, int N>
 __global__ __launch_bounds__(256) void k1_z_kernel(const Tin* __restrict__ delta, cplx<T>* __restrict__ F,
                                                    const cplx<T>* __restrict__ tw, FftShape sh, int tb, int nkeep,
                                                    T scale) {
   extern __shared__ char smem_raw[];
-  const int n = sh.n;
+  const int n = N > 0 ? N : sh.n;
+  const int tb_shift = __builtin_ctz(unsigned(tb));  // tb is a power of two
   const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw_l + n;
@@ -45,20 +47,24 @@ __global__ __launch_bounds__(256) void k1_z_kernel(const Tin* __restrict__ delta
     b0[l * ls + i] = {T(src[q]) * scale, T(0)};
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
+  cplx<T>* res;
+  if constexpr (N > 0)
+    res = lds_fft_c<T, N>(b0, b1, tw_l, tb, ls);
+  else
+    res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   cplx<T>* dst = F + size_t(b) * nkeep * n * n + size_t(x) * n + y0;
   for (int q = threadIdx.x; q < tb * nkeep; q += blockDim.x) {
-    const int kz = q / tb, l = q - kz * tb;
+    const int kz = q >> tb_shift, l = q & (tb - 1);
     dst[size_t(kz) * n * n + l] = res[l * ls + kz];
   }
 }
 
 // In-place transform of contiguous lines: line i of `lines` at base + i * n.
-template <typename T>
+template <typename T, int N>
 __global__ __launch_bounds__(256) void k_rows_kernel(cplx<T>* __restrict__ data, const cplx<T>* __restrict__ tw,
                                                      FftShape sh, int tb, long lines_total) {
   extern __shared__ char smem_raw[];
-  const int n = sh.n;
+  const int n = N > 0 ? N : sh.n;
   const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw_l + n;
@@ -72,7 +78,11 @@ __global__ __launch_bounds__(256) void k_rows_kernel(cplx<T>* __restrict__ data,
     b0[l * ls + i] = base[q];
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, lines, ls);
+  cplx<T>* res;
+  if constexpr (N > 0)
+    res = lds_fft_c<T, N>(b0, b1, tw_l, lines, ls);
+  else
+    res = lds_fft(b0, b1, tw_l, sh, lines, ls);
   for (int q = threadIdx.x; q < lines * n; q += blockDim.x) {
     const int l = q / n, i = q - l * n;
     base[q] = res[l * ls + i];
@@ -81,11 +91,12 @@ __global__ __launch_bounds__(256) void k_rows_kernel(cplx<T>* __restrict__ data,
 
 // In-place transform of strided lines: for each plane p (grid.y), the lines are
 // the columns c of an n x n array (element i at i * n + c); `tb` columns per block.
-template <typename T>
+template <typename T, int N>
 __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data, const cplx<T>* __restrict__ tw,
                                                      FftShape sh, int tb) {
   extern __shared__ char smem_raw[];
-  const int n = sh.n;
+  const int n = N > 0 ? N : sh.n;
+  const int tb_shift = __builtin_ctz(unsigned(tb));  // tb is a power of two
   const int ls = n + 1;  // padded line stride: transposed accesses hit different banks
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b0 = tw_l + n;
@@ -94,13 +105,17 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
   const int c0 = blockIdx.x * tb;
   cplx<T>* base = data + size_t(blockIdx.y) * n * n + c0;
   for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
-    const int i = q / tb, l = q - i * tb;
+    const int i = q >> tb_shift, l = q & (tb - 1);
     b0[l * ls + i] = base[size_t(i) * n + l];
   }
   __syncthreads();
-  cplx<T>* res = lds_fft(b0, b1, tw_l, sh, tb, ls);
+  cplx<T>* res;
+  if constexpr (N > 0)
+    res = lds_fft_c<T, N>(b0, b1, tw_l, tb, ls);
+  else
+    res = lds_fft(b0, b1, tw_l, sh, tb, ls);
   for (int q = threadIdx.x; q < tb * n; q += blockDim.x) {
-    const int i = q / tb, l = q - i * tb;
+    const int i = q >> tb_shift, l = q & (tb - 1);
     base[size_t(i) * n + l] = res[l * ls + i];
   }
 }
