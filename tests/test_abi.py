@@ -63,6 +63,16 @@ def test_host_errors():
     with pytest.raises(bk.BkError) as e:
         bk.bk_count_triangles(bk.make_binning(16, 3, 2.0, 5.0, 5, 3, l_max=14))
     assert e.value.status == bk.BK_ERR_ARG
+    # every l up to 12 would be 91 outputs; a plan holds at most 64
+    with pytest.raises(bk.BkError) as e:
+        bk.bk_count_triangles(bk.make_binning(16, 3, 2.0, 5.0, 5, 3, l_max=12, m_max=12, even_l_only=0))
+    assert e.value.status == bk.BK_ERR_ARG and "64" in bk.bk_last_error()
+    with pytest.raises(bk.BkError) as e:
+        bk.bk_count_triangles(bk.make_binning(16, 3, 2.0, 5.0, 5, 3, even_l_only=2))
+    assert e.value.status == bk.BK_ERR_ARG
+    # 9 x 10 / 2 = 45 outputs with every l <= 8 is accepted
+    counts, n_comb = bk.bk_count_triangles(bk.make_binning(16, 3, 2.0, 5.0, 5, 3, l_max=8, m_max=8, even_l_only=0))
+    assert n_comb > 0
     b = bk.make_binning(16, 3, 2.0, 5.0, 5, 3)
     st = bk.lib().bk_count_triangles(ctypes.byref(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 4, None)
     assert st == bk.BK_ERR_SIZE and "small" in bk.bk_last_error()

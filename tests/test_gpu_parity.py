@@ -369,6 +369,9 @@ EDGE_CASES = [
     # m_max < l_max (13 outputs)
     ("mmax2", dict(ng=24, n_k1=2, k1_min=3.0, k1_max=8.0, n_mu=3, n_t=3, l_max=8, m_max=2),
      FieldRecipe(24, n_s=-2.0, f_ng=0.5, beta=0.5, seed=23)),
+    # every l <= 8 (45 outputs: the 64-lane binning path with odd-l lanes)
+    ("lmax8_all", dict(ng=24, n_k1=2, k1_min=3.0, k1_max=8.0, n_mu=3, n_t=3, l_max=8, m_max=8, even=False),
+     FieldRecipe(24, n_s=-1.5, f_ng=0.5, beta=1.0, seed=25)),
     # fine (mu, t) bins at a small grid: many empty bins (NaN pattern)
     ("empty", dict(ng=16, n_k1=3, k1_min=2.5, k1_max=5.0, n_mu=9, n_t=9),
      FieldRecipe(16, n_s=-2.0, f_ng=0.5, beta=0.5, seed=24)),
@@ -384,12 +387,14 @@ def test_edge_case_parity(case, prec):
 
     name, kw, recipe = EDGE_CASES[case]
     _say(f"edge case {name} prec={prec}")
+    even = kw.get("even", True)
     b = Binning(kw["ng"], kw["n_k1"], kw["k1_min"], kw["k1_max"], kw["n_mu"], kw["n_t"],
-                l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6))
+                l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6), even_l_only=even)
     delta = make_field(recipe)
     ref = estimate(delta, b)
     est = bk.Estimator(bk.make_binning(kw["ng"], kw["n_k1"], kw["k1_min"], kw["k1_max"], kw["n_mu"], kw["n_t"],
-                                       l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6)), prec=prec)
+                                       l_max=kw.get("l_max", 6), m_max=kw.get("m_max", 6), even_l_only=int(even)),
+                       prec=prec)
     try:
         s = torch.cuda.current_stream().cuda_stream
         est.load(torch.from_numpy(delta).cuda(), s)
