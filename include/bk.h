@@ -90,7 +90,11 @@ typedef struct {
 
 /* Build the geometry tables (rings, N_tri, combinations, weights, bins) on the
  * host and allocate the device working set on `device` for up to `max_batch`
- * fields of this size.  prec selects float32 (BK_F32: FFTs, D and the products
+ * fields of this size.  The tables are the paper's first-level geometry: the
+ * plane x annular-ring cells with the ring widths of Sec. II's implementation
+ * paragraph, N_tri of Eq. 10 per ring triple, the shape (Eq. 2) and
+ * orientation (Eq. 3) of every combination, and its (k1, mu, t) bin and Y
+ * weights for Eq. 13.  prec selects float32 (BK_F32: FFTs, D and the products
  * in float32, blocked float32 partial sums combined in float64) or float64
  * (BK_F64: every step in float64).  The final per-bin sums are float64 in both.
  * Setting the environment variable BK_FULL_GRID=1 sums every combination on
@@ -104,7 +108,8 @@ bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int ma
 bk_status bk_plan_destroy(bk_plan plan);
 
 /* Copy `batch` fields delta(x), C order [batch][x][y][z] (z = line of sight),
- * of type dtype (BK_F32 or BK_F64), into the plan.  `delta` is a device pointer
+ * of type dtype (BK_F32 or BK_F64), into the plan: the gridded redshift-space
+ * field delta^s(x) of Sec. II on N_g^3 cells of the periodic box V = L^3.  `delta` is a device pointer
  * if is_device_ptr != 0, else a host pointer.  The copy is enqueued on
  * hip_stream (a hipStream_t, NULL = default stream); a device input must stay
  * valid until the stream reaches this point. */
@@ -112,9 +117,19 @@ bk_status bk_load_grid(bk_plan plan, const void* delta, int dtype, int batch, in
                        void* hip_stream);
 
 /* Enqueue the whole estimator for the loaded fields on hip_stream:
- * forward FFT, ring-masked 2-D FFTs (Step I), triple-product sums (Step II)
- * and the binned multipoles.  Asynchronous; results are read with get_*. */
+ * forward FFT, ring-masked 2-D FFTs (Step I, Eq. 9), triple-product sums
+ * (Step II, Eq. 8) and the binned multipoles (Eq. 13).  Asynchronous; results
+ * are read with get_*.  The plan's kernels are captured once into a hipGraph
+ * (again when the loaded batch size, the input type or the tile choices
+ * change) and every call replays it with one hipGraphLaunch; the graph
+ * records no per-stage events, so bk_get_stage_times needs
+ * bk_estimate_timed. */
 bk_status bk_estimate(bk_plan plan, void* hip_stream);
+
+/* The same estimate launched kernel by kernel, with hipEvents recorded on
+ * hip_stream between the four stages (read them with bk_get_stage_times).
+ * Results are identical to bk_estimate's. */
+bk_status bk_estimate_timed(bk_plan plan, void* hip_stream);
 
 /* Wait for all work the plan enqueued. */
 bk_status bk_synchronize(bk_plan plan);
@@ -126,14 +141,20 @@ bk_status bk_query_sizes(bk_plan plan, int* n_lm, int* n_k1, int* n_mu, int* n_t
 bk_status bk_get_lm_list(bk_plan plan, int* lm_pairs, size_t cap);
 
 /* B_l^m as float64 [batch][n_lm][n_k1][n_mu][n_t] for the last estimate
- * (synchronises the plan's stream).  cap >= batch * n_lm * n_bins. */
+ * (synchronises the plan's stream): the bin averages of Eq. 13,
+ * sqrt((2l+1)/4pi) sum Y* B_hat N_tri / sum |Y|^2 N_tri over the bin's
+ * combinations, with B_hat N_tri = S / (V N_g^2) from Eq. 8.  NaN where a bin
+ * holds no combination.  cap >= batch * n_lm * n_bins. */
 bk_status bk_get_multipoles(bk_plan plan, double* out, size_t cap);
 
-/* Sum of N_tri over the combinations of each bin, int64 [n_k1][n_mu][n_t].
- * Geometry only (independent of the field); exact. */
+/* Sum of N_tri (Eq. 10: ordered (u, v, w) with u + v + w = 0 in the three
+ * rings) over the combinations of each bin, a combination and its n -> -n
+ * partner both counted, int64 [n_k1][n_mu][n_t].  Geometry only (independent
+ * of the field); exact. */
 bk_status bk_get_triangle_counts(bk_plan plan, int64_t* out, size_t cap);
 
-/* N_tri-weighted mean (k1, mu, t) of each bin, float64 [n_bins][3]; NaN if empty. */
+/* N_tri-weighted mean (k1, mu, t) of each bin (Eq. 2 on the combinations'
+ * mean-value sides, weighted as in Eq. 13), float64 [n_bins][3]; NaN if empty. */
 bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
 
 /* Plan statistics, float64 [cap] with 9 <= cap (11 filled at most):
@@ -145,8 +166,13 @@ bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
  * one grid size), complex elements of D per field. */
 bk_status bk_get_plan_info(bk_plan plan, double* info, size_t cap);
 
-/* Device time of each stage of the last estimate in milliseconds, float64 [4]:
- * forward FFT, ring FFTs, triple products, binning (hipEvents on the stream). */
+/* Device time of each stage in milliseconds, float64 [4]: forward FFT, ring
+ * FFTs, triple products, binning (hipEvents recorded on the stream around
+ * each stage), averaged over the consecutive timed estimates
+ * (bk_estimate_timed) since the last bk_estimate or bk_load_grid, the latest
+ * 32 at most.  With cap >= 5, out[4] receives the number averaged.
+ * bk_plan_autotune and a bk_debug_set_D estimate leave one timed estimate.
+ * BK_ERR_STATE if there is none. */
 bk_status bk_get_stage_times(bk_plan plan, double* ms, size_t cap);
 
 /* Tile autotuning.  With a grid loaded, times every valid tile choice of the
@@ -220,11 +246,27 @@ bk_status bk_continuum_multipoles(int l_max, int m_max, double mu, double t, dou
  * (a stored side n >= 0 on one grid size m), complex [batch][sum of m^2] with
  * the grid sides one after the other, x_perp index x * m + y; 2: the grid-side
  * table in that order, int32 [grid sides][3] = (ring, n, m); 3, 4, 5: the contraction's work
- * items, workgroups and staged-side lists as stored on the host (raw bytes).
+ * items, workgroups and staged-side lists as stored on the host (raw bytes);
+ * 6: the contraction outputs, float64 [batch][work item][cells], per item Re S
+ * of cell (pair p, slot-B ring j) at p * 16 + j, then Im S of every cell when
+ * odd l are requested (S = sum over the item's m x m grid of
+ * D_A D_B conj(D_C) in the units of buffer 1; Eq. 8 on that grid).
  * Elements of 0 and 1 are float32 pairs for BK_F32 plans, float64 pairs for
  * BK_F64.  *needed receives the size in bytes; BK_ERR_SIZE if cap_bytes is
  * smaller.  Buffers 2-5 do not need a device. */
 bk_status bk_debug_get_buffer(bk_plan plan, int which, void* out, size_t cap_bytes, size_t* needed);
+
+/* Test support: copy `bytes` bytes from offset_bytes of device buffer 0, 1 or
+ * 6 (as in bk_debug_get_buffer) of the last estimate into host memory, so
+ * large grids can be sampled.  BK_ERR_SIZE if the range leaves the buffer. */
+bk_status bk_debug_read_range(bk_plan plan, int which, size_t offset_bytes, void* out, size_t bytes);
+
+/* Test support: set the ring sums D (Eq. 9) of `batch` fields directly, in the
+ * layout and units of bk_debug_get_buffer's buffer 1 (complex of the plan's
+ * precision), from a host or device pointer; the next bk_estimate then runs
+ * only the triple products (Eq. 8) and the binning (Eq. 13) on it, as a
+ * timed eager launch.  The copy is enqueued on hip_stream. */
+bk_status bk_debug_set_D(bk_plan plan, const void* D, int batch, int is_device_ptr, void* hip_stream);
 
 /* Test support: runs one 16x16x4 MFMA of the given precision (BK_F32 or BK_F64)
  * with A[i][k] = i + 16 k and B[k][j] = 1 if j == k else 0 (k < 4), and returns

@@ -67,6 +67,7 @@ _SIGS = {
     "bk_plan_destroy": [ctypes.c_void_p],
     "bk_load_grid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "bk_estimate": [ctypes.c_void_p, ctypes.c_void_p],
+    "bk_estimate_timed": [ctypes.c_void_p, ctypes.c_void_p],
     "bk_synchronize": [ctypes.c_void_p],
     "bk_query_sizes": [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bk_get_lm_list": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_size_t],
@@ -79,6 +80,8 @@ _SIGS = {
     "bk_debug_get_buffer": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                             ctypes.POINTER(ctypes.c_size_t)],
     "bk_debug_mfma_probe": [ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+    "bk_debug_read_range": [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_size_t],
+    "bk_debug_set_D": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "bk_group_create": [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
     "bk_group_estimate": [ctypes.c_void_p, ctypes.c_void_p],
     "bk_group_destroy": [ctypes.c_void_p],
@@ -141,6 +144,10 @@ def bk_estimate(plan: int, stream: int = 0):
     _check(lib().bk_estimate(ctypes.c_void_p(plan), ctypes.c_void_p(stream)))
 
 
+def bk_estimate_timed(plan: int, stream: int = 0):
+    _check(lib().bk_estimate_timed(ctypes.c_void_p(plan), ctypes.c_void_p(stream)))
+
+
 def bk_synchronize(plan: int):
     _check(lib().bk_synchronize(ctypes.c_void_p(plan)))
 
@@ -197,6 +204,13 @@ def bk_get_stage_times(plan: int) -> list:
     return out.tolist()
 
 
+def bk_get_stage_times_count(plan: int) -> list:
+    """The four stage times and, fifth, the number of timed estimates averaged."""
+    out = np.empty(5, dtype=np.float64)
+    _check(lib().bk_get_stage_times(ctypes.c_void_p(plan), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 5))
+    return out.tolist()
+
+
 def bk_plan_autotune(plan: int, stream: int = 0) -> list:
     out = (ctypes.c_int * 3)()
     _check(lib().bk_plan_autotune(ctypes.c_void_p(plan), ctypes.c_void_p(stream), out))
@@ -238,11 +252,38 @@ def bk_debug_get_buffer(plan: int, which: int, prec: int) -> np.ndarray:
         out = np.empty(need.value // 4, dtype=np.int32)
     elif which == 3:
         out = np.empty(need.value, dtype=np.uint8)
+    elif which == 6:
+        out = np.empty(need.value // 8, dtype=np.float64)
     else:
         out = np.empty(need.value // (8 if prec == BK_F32 else 16), dtype=np.complex64 if prec == BK_F32 else np.complex128)
     _check(lib().bk_debug_get_buffer(ctypes.c_void_p(plan), int(which), ctypes.c_void_p(out.ctypes.data), out.nbytes,
                                      ctypes.byref(need)))
     return out
+
+
+def bk_debug_get_buffer_size(plan: int, which: int) -> int:
+    """Size in bytes of a test-support buffer (see bk_debug_get_buffer)."""
+    need = ctypes.c_size_t()
+    _check(lib().bk_debug_get_buffer(ctypes.c_void_p(plan), int(which), None, 0, ctypes.byref(need)))
+    return need.value
+
+
+def bk_debug_read_range(plan: int, which: int, prec: int, offset: int, count: int) -> np.ndarray:
+    """`count` elements from element `offset` of buffer 0 or 1 (complex of the
+    plan's precision) or 6 (float64)."""
+    if which == 6:
+        dt = np.dtype(np.float64)
+    else:
+        dt = np.dtype(np.complex64 if prec == BK_F32 else np.complex128)
+    out = np.empty(int(count), dtype=dt)
+    _check(lib().bk_debug_read_range(ctypes.c_void_p(plan), int(which), int(offset) * dt.itemsize,
+                                     ctypes.c_void_p(out.ctypes.data), out.nbytes))
+    return out
+
+
+def bk_debug_set_D(plan: int, ptr: int, batch: int, is_device_ptr: bool, stream: int = 0):
+    _check(lib().bk_debug_set_D(ctypes.c_void_p(plan), ctypes.c_void_p(ptr), int(batch), int(bool(is_device_ptr)),
+                                ctypes.c_void_p(stream)))
 
 
 def bk_debug_mfma_probe(prec: int) -> np.ndarray:
@@ -309,6 +350,9 @@ class Estimator:
 
     def estimate(self, stream: int = 0):
         bk_estimate(self.plan, stream)
+
+    def estimate_timed(self, stream: int = 0):
+        bk_estimate_timed(self.plan, stream)
 
     def multipoles(self) -> np.ndarray:
         return bk_get_multipoles(self.plan, self.batch)

@@ -64,7 +64,6 @@ struct bk_plan_s {
   int batch = 0;          // fields currently loaded
   int in_dtype = 0;       // dtype of the loaded fields
   int estimated = 0;      // a completed estimate is enqueued for `batch`
-  int timed = 0;          // the stage events belong to the last estimate
   hipStream_t stream = nullptr;
   size_t elem = 8;        // sizeof(complex T) / 2
   bk::FftShape sh{};
@@ -109,8 +108,23 @@ struct bk_plan_s {
   int32_t* d_combo_slot = nullptr;
   void* d_coef = nullptr;         // per-combination coefficients, float32 (BK_F32 plans) or float64
   unsigned char* d_empty = nullptr;
-  hipEvent_t ev[5] = {};
+  // Stage events: launch_all records the five stage boundaries into `ev`,
+  // which points at one of kEvSets sets used in turn by consecutive timed
+  // estimates; ev_count sets (the latest ones) belong to timed estimates of
+  // the current results (0 after a graph replay).
+  static constexpr int kEvSets = 32;
+  hipEvent_t evs[kEvSets][5] = {};
+  hipEvent_t* ev = evs[0];
+  int ev_next = 0;
+  int ev_count = 0;
   bool have_events = false;
+  int d_injected = 0;     // D was set by bk_debug_set_D: the next estimate starts at the contraction
+  // bk_estimate replays the plan's kernels from a graph captured on cap_stream
+  // for the launch configuration graph_key (recaptured when it changes)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::array<long, 6> graph_key{};
 };
 
 namespace {
@@ -160,7 +174,41 @@ void release(bk_plan p) {
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (p->have_events)
-    for (auto& e : p->ev) (void)hipEventDestroy(e);
+    for (auto& set : p->evs)
+      for (auto& e : set)
+        if (e) (void)hipEventDestroy(e);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+}
+
+// Device buffers one estimate reads and writes.  The plan's own (bk_estimate)
+// or caller input/output with the library's static scratch
+// (bk_estimate_noalloc).
+struct Bufs {
+  const void* in = nullptr;  // [batch][N^3] fields of in_dtype
+  int in_dtype = 0;
+  int batch = 0;
+  void* F = nullptr;         // [batch][nkeep][N][N] complex
+  void* D = nullptr;         // [batch][d_elems] complex
+  double* S = nullptr;       // [batch][n_items][item_out]
+  double* part = nullptr;    // [batch][n_chunks][n_lm]
+  double* B = nullptr;       // [batch][n_lm][n_bins]
+  bool skip_fft = false;     // D is already set: run the contraction and the binning only
+};
+
+Bufs plan_bufs(bk_plan p) {
+  Bufs b;
+  b.in = p->d_in;
+  b.in_dtype = p->in_dtype;
+  b.batch = p->batch;
+  b.F = p->d_F;
+  b.D = p->d_D;
+  b.S = p->d_S;
+  b.part = p->d_part;
+  b.B = p->d_B;
+  b.skip_fft = p->d_injected != 0;
+  return b;
 }
 
 template <typename T>
@@ -169,10 +217,13 @@ constexpr bool prec_is_f32() {
 }
 
 // LDS bytes of the contraction for a chunk of ch points (two buffers of every
-// staged slot plus the zero slot), 0 if the chunk does not divide every grid
+// staged slot plus the zero slot), 0 if the kernel has no instance for the
+// chunk (float32: 32 or 64 points, float64: 16 or 32), if it does not divide every grid
 // level's m^2 points, gives fewer than 16 16-byte units per slot, needs more
 // staging lines than the kernel issues, or exceeds the 160 KiB of a CU.
 size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
+  // the chunks the contraction kernel is instantiated for
+  if (prec == BK_F32 ? (ch != 32 && ch != 64) : (ch != 16 && ch != 32)) return 0;
   const size_t cs = prec == BK_F32 ? 8 : 16;
   const int units = int(size_t(ch) * cs / 16);
   if (units < 16 || units % 16 != 0) return 0;
@@ -206,16 +257,16 @@ int pick_tb(int n, size_t elem_bytes) {
     if (p->tab.bin.even_l_only)                                                                                  \
       hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW, false>), g3, dim3(bk::kK3Threads), p->lds_k3, \
                          st, D, long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides,      \
-                         p->d_S, p->n_items);                                                                    \
+                         S, p->n_items);                                                                         \
     else                                                                                                         \
       hipLaunchKernelGGL((bk::k3_contract_kernel<TT, CHV, TPI, IPW, true>), g3, dim3(bk::kK3Threads), p->lds_k3,  \
                          st, D, long(p->tab.d_elems), p->d_gs_off, p->d_groups, p->d_items, p->d_group_sides,      \
-                         p->d_S, p->n_items);                                                                    \
+                         S, p->n_items);                                                                         \
   } while (0)
 
 // Contraction launch for the plan's item shape (row tiles per item, items per wave).
 template <typename T, int CH>
-void launch_k3_shape(bk_plan p, const bk::cplx<T>* D, dim3 g3, hipStream_t st) {
+void launch_k3_shape(bk_plan p, const bk::cplx<T>* D, double* S, dim3 g3, hipStream_t st) {
   const int tpi = p->tab.k3.pairs_per_item / bk::kTileN;
   if (p->tab.k3.items_per_wave == 2)
     BK_K3(T, CH, 1, 2);
@@ -228,67 +279,73 @@ void launch_k3_shape(bk_plan p, const bk::cplx<T>* D, dim3 g3, hipStream_t st) {
 }
 
 // ... and the plan's chunk (one of the two k3_lds_bytes allows per precision).
-void launch_k3(bk_plan p, const bk::cplx<float>* D, dim3 g3, hipStream_t st) {
+bk_status launch_k3(bk_plan p, const bk::cplx<float>* D, double* S, dim3 g3, hipStream_t st) {
   if (p->k3_chunk == 64)
-    launch_k3_shape<float, 64>(p, D, g3, st);
+    launch_k3_shape<float, 64>(p, D, S, g3, st);
+  else if (p->k3_chunk == 32)
+    launch_k3_shape<float, 32>(p, D, S, g3, st);
   else
-    launch_k3_shape<float, 32>(p, D, g3, st);
+    return fail(BK_ERR_ARG, "internal: no float32 contraction instance for this chunk");
+  return BK_OK;
 }
 
-void launch_k3(bk_plan p, const bk::cplx<double>* D, dim3 g3, hipStream_t st) {
+bk_status launch_k3(bk_plan p, const bk::cplx<double>* D, double* S, dim3 g3, hipStream_t st) {
   if (p->k3_chunk == 32)
-    launch_k3_shape<double, 32>(p, D, g3, st);
+    launch_k3_shape<double, 32>(p, D, S, g3, st);
+  else if (p->k3_chunk == 16)
+    launch_k3_shape<double, 16>(p, D, S, g3, st);
   else
-    launch_k3_shape<double, 16>(p, D, g3, st);
+    return fail(BK_ERR_ARG, "internal: no float64 contraction instance for this chunk");
+  return BK_OK;
 }
 #undef BK_K3
 
 // The three K1 passes for a transform length N known at compile time (0: any).
 template <typename T, int N>
-void launch_k1(bk_plan p, bk::cplx<T>* F, const bk::cplx<T>* tw, int tb, size_t lds, hipStream_t st) {
+void launch_k1(bk_plan p, const Bufs& bf, bk::cplx<T>* F, const bk::cplx<T>* tw, int tb, size_t lds, hipStream_t st) {
   const int n = p->sh.n;
-  const int B = p->batch;
+  const int B = bf.batch;
   dim3 grid(n * (n / tb), B);
-  if (p->in_dtype == BK_F32)
+  if (bf.in_dtype == BK_F32)
     hipLaunchKernelGGL((bk::k1_z_kernel<T, float, N>), grid, dim3(256), lds, st,
-                       reinterpret_cast<const float*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+                       reinterpret_cast<const float*>(bf.in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
   else
     hipLaunchKernelGGL((bk::k1_z_kernel<T, double, N>), grid, dim3(256), lds, st,
-                       reinterpret_cast<const double*>(p->d_in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
+                       reinterpret_cast<const double*>(bf.in), F, tw, p->sh, tb, p->nkeep, T(p->delta_scale));
   const long lines = long(B) * p->nkeep * n;
   hipLaunchKernelGGL((bk::k_rows_kernel<T, N>), dim3((lines + tb - 1) / tb), dim3(256), lds, st, F, tw, p->sh, tb,
                      lines);
   hipLaunchKernelGGL((bk::k_cols_kernel<T, N>), dim3(n / tb, B * p->nkeep), dim3(256), lds, st, F, tw, p->sh, tb);
 }
 
+// K1 and K2: the forward FFT of the fields, then the ring sums D of every
+// grid side (ev[1] between them when timing).
 template <typename T>
-bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
+bk_status launch_fft(bk_plan p, const Bufs& bf, hipStream_t st, bool timing) {
   using C = bk::cplx<T>;
   const int n = p->sh.n;
-  const int B = p->batch;
+  const int B = bf.batch;
   const size_t cs = sizeof(C);
   const int tb = p->fft_tb > 0 ? p->fft_tb : pick_tb(n, cs);
   const size_t lds_fft = fft_lds_bytes(n, tb, cs);
   const C* tw = reinterpret_cast<const C*>(p->d_tw);
-  C* F = reinterpret_cast<C*>(p->d_F);
-  C* D = reinterpret_cast<C*>(p->d_D);
-
-  if (timing) BK_HIP(hipEventRecord(p->ev[0], st));
+  C* F = reinterpret_cast<C*>(bf.F);
+  C* D = reinterpret_cast<C*>(bf.D);
   // K1: z pass (real input), y rows, x columns; one instance per supported N_g
   switch (n) {
-    case 8: launch_k1<T, 8>(p, F, tw, tb, lds_fft, st); break;
-    case 16: launch_k1<T, 16>(p, F, tw, tb, lds_fft, st); break;
-    case 24: launch_k1<T, 24>(p, F, tw, tb, lds_fft, st); break;
-    case 32: launch_k1<T, 32>(p, F, tw, tb, lds_fft, st); break;
-    case 48: launch_k1<T, 48>(p, F, tw, tb, lds_fft, st); break;
-    case 64: launch_k1<T, 64>(p, F, tw, tb, lds_fft, st); break;
-    case 96: launch_k1<T, 96>(p, F, tw, tb, lds_fft, st); break;
-    case 128: launch_k1<T, 128>(p, F, tw, tb, lds_fft, st); break;
-    case 192: launch_k1<T, 192>(p, F, tw, tb, lds_fft, st); break;
-    case 256: launch_k1<T, 256>(p, F, tw, tb, lds_fft, st); break;
-    case 384: launch_k1<T, 384>(p, F, tw, tb, lds_fft, st); break;
-    case 512: launch_k1<T, 512>(p, F, tw, tb, lds_fft, st); break;
-    default: launch_k1<T, 0>(p, F, tw, tb, lds_fft, st);
+    case 8: launch_k1<T, 8>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 16: launch_k1<T, 16>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 24: launch_k1<T, 24>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 32: launch_k1<T, 32>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 48: launch_k1<T, 48>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 64: launch_k1<T, 64>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 96: launch_k1<T, 96>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 128: launch_k1<T, 128>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 192: launch_k1<T, 192>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 256: launch_k1<T, 256>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 384: launch_k1<T, 384>(p, bf, F, tw, tb, lds_fft, st); break;
+    case 512: launch_k1<T, 512>(p, bf, F, tw, tb, lds_fft, st); break;
+    default: launch_k1<T, 0>(p, bf, F, tw, tb, lds_fft, st);
   }
   BK_HIP(hipGetLastError());
   if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
@@ -332,11 +389,28 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
       BK_HIP(hipGetLastError());
     }
   }
+  return BK_OK;
+}
+
+template <typename T>
+bk_status launch_all(bk_plan p, const Bufs& bf, hipStream_t st, bool timing) {
+  using C = bk::cplx<T>;
+  const int B = bf.batch;
+  const C* D = reinterpret_cast<const C*>(bf.D);
+
+  if (timing) BK_HIP(hipEventRecord(p->ev[0], st));
+  if (!bf.skip_fft) {
+    bk_status s12 = launch_fft<T>(p, bf, st, timing);
+    if (s12 != BK_OK) return s12;
+  } else if (timing) {
+    BK_HIP(hipEventRecord(p->ev[1], st));
+  }
   if (timing) BK_HIP(hipEventRecord(p->ev[2], st));
   // K3: triple products
   if (!p->tab.groups.empty()) {
     dim3 g3(p->tab.groups.size(), B);
-    launch_k3(p, D, g3, st);
+    bk_status s3 = launch_k3(p, D, bf.S, g3, st);
+    if (s3 != BK_OK) return s3;
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[3], st));
@@ -353,22 +427,86 @@ bk_status launch_all(bk_plan p, hipStream_t st, bool timing) {
     if (p->n_chunks > 0) {
       dim3 gp(p->n_chunks, B);
       if (nlm <= 16)
-        hipLaunchKernelGGL((bk::k4_partial_kernel<16, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<16, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
       else if (nlm <= 32)
-        hipLaunchKernelGGL((bk::k4_partial_kernel<32, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<32, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
       else
-        hipLaunchKernelGGL((bk::k4_partial_kernel<64, T>), gp, dim3(64), 0, st, p->d_S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, p->d_part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<64, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
+                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
       BK_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, p->d_part, p->n_chunks, p->d_bin_chunk, p->d_empty,
-                       nlm, n_bins, p->norm, p->d_B);
+    hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, bf.part, p->n_chunks, p->d_bin_chunk, p->d_empty,
+                       nlm, n_bins, p->norm, bf.B);
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[4], st));
   return BK_OK;
+}
+
+// Capture the plan's launches (full path, no stage events) into its graph,
+// unless the graph already matches the launch configuration.
+bk_status plan_graph(bk_plan p) {
+  const std::array<long, 6> key = {long(p->batch), long(p->in_dtype), long(p->fft_tb), long(p->k2_tb),
+                                   long(p->k3_chunk), long(p->lds_k3)};
+  if (p->graph_exec && key == p->graph_key) return BK_OK;
+  if (!p->cap_stream) BK_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  if (p->graph_exec) {
+    BK_HIP(hipGraphExecDestroy(p->graph_exec));
+    p->graph_exec = nullptr;
+  }
+  if (p->graph) {
+    BK_HIP(hipGraphDestroy(p->graph));
+    p->graph = nullptr;
+  }
+  BK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  Bufs bf = plan_bufs(p);
+  bf.skip_fft = false;
+  bk_status st = p->prec == BK_F32 ? launch_all<float>(p, bf, p->cap_stream, false)
+                                   : launch_all<double>(p, bf, p->cap_stream, false);
+  hipGraph_t graph = nullptr;
+  hipError_t he = hipStreamEndCapture(p->cap_stream, &graph);
+  if (st != BK_OK || he != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st != BK_OK ? st : fail(BK_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(he));
+  }
+  p->graph = graph;
+  BK_HIP(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  p->graph_key = key;
+  return BK_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// One eager estimate with stage events into the next event set.
+bk_status timed_launch(bk_plan p, const Bufs& bf, hipStream_t st) {
+  p->ev = p->evs[p->ev_next];
+  bk_status s = p->prec == BK_F32 ? launch_all<float>(p, bf, st, true) : launch_all<double>(p, bf, st, true);
+  if (s != BK_OK) return s;
+  p->ev_next = (p->ev_next + 1) % bk_plan_s::kEvSets;
+  p->ev_count = std::min(p->ev_count + 1, bk_plan_s::kEvSets);
+  return BK_OK;
+}
+
+// Base and size (bytes) of a plan's device buffer for the loaded batch:
+// 0 Delta planes, 1 D, 6 contraction outputs S.
+void device_buffer(bk_plan p, int which, const void** src, size_t* bytes) {
+  const size_t cs = 2 * p->elem;
+  const size_t n2 = size_t(p->sh.n) * p->sh.n;
+  const size_t b = size_t(std::max(p->batch, 0));
+  if (which == 0) {
+    *src = p->d_F;
+    *bytes = b * p->nkeep * n2 * cs;
+  } else if (which == 1) {
+    *src = p->d_D;
+    *bytes = b * size_t(p->tab.d_elems) * cs;
+  } else {
+    *src = p->d_S;
+    *bytes = b * size_t(p->n_items) * size_t(p->item_out) * sizeof(double);
+  }
 }
 
 }  // namespace
@@ -708,15 +846,16 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
       p->tuned = 1;
     }
   }
-  for (auto& e : p->ev) {
-    hipError_t he = hipEventCreate(&e);
-    if (he != hipSuccess) {
-      release(p);
-      delete p;
-      return fail(BK_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
-    }
-  }
   p->have_events = true;
+  for (auto& set : p->evs)
+    for (auto& e : set) {
+      hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) {
+        release(p);
+        delete p;
+        return fail(BK_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+      }
+    }
   *out = p;
   return BK_OK;
 }
@@ -748,6 +887,8 @@ bk_status bk_load_grid(bk_plan p, const void* delta, int dtype, int batch, int i
   p->batch = batch;
   p->in_dtype = dtype;
   p->estimated = 0;
+  p->ev_count = 0;
+  p->d_injected = 0;
   p->stream = st;
   return BK_OK;
 }
@@ -758,11 +899,35 @@ bk_status bk_estimate(bk_plan p, void* hip_stream) {
   if (p->batch < 1) return fail(BK_ERR_STATE, "no grid loaded");
   BK_HIP(hipSetDevice(p->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  bk_status s = p->prec == BK_F32 ? launch_all<float>(p, st, true) : launch_all<double>(p, st, true);
-  if (s != BK_OK) return s;
+  if (p->d_injected) {
+    // test support: D was set directly, run the contraction and binning eagerly
+    p->ev_count = 0;
+    bk_status s = timed_launch(p, plan_bufs(p), st);
+    if (s != BK_OK) return s;
+    p->d_injected = 0;
+  } else {
+    bk_status s = plan_graph(p);
+    if (s != BK_OK) return s;
+    BK_HIP(hipGraphLaunch(p->graph_exec, st));
+    p->ev_count = 0;
+  }
   p->stream = st;
   p->estimated = 1;
-  p->timed = 1;
+  return BK_OK;
+}
+
+bk_status bk_estimate_timed(bk_plan p, void* hip_stream) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  if (p->batch < 1) return fail(BK_ERR_STATE, "no grid loaded");
+  BK_HIP(hipSetDevice(p->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  if (p->d_injected) p->ev_count = 0;
+  bk_status s = timed_launch(p, plan_bufs(p), st);
+  if (s != BK_OK) return s;
+  p->d_injected = 0;
+  p->stream = st;
+  p->estimated = 1;
   return BK_OK;
 }
 
@@ -847,31 +1012,33 @@ bk_status bk_get_stage_times(bk_plan p, double* ms, size_t cap) {
   g_last_error.clear();
   if (!p || !ms) return fail(BK_ERR_ARG, "null argument");
   if (cap < 4) return fail(BK_ERR_SIZE, "need 4 entries");
-  if (!p->estimated || !p->timed) return fail(BK_ERR_STATE, "no individually launched estimate has been run");
+  if (!p->estimated || p->ev_count == 0) return fail(BK_ERR_STATE, "no timed estimate has been run");
   BK_HIP(hipSetDevice(p->device));
-  BK_HIP(hipEventSynchronize(p->ev[4]));
-  for (int i = 0; i < 4; ++i) {
-    float t = 0.f;
-    BK_HIP(hipEventElapsedTime(&t, p->ev[i], p->ev[i + 1]));
-    ms[i] = double(t);
+  const int K = bk_plan_s::kEvSets;
+  const int last = (p->ev_next + K - 1) % K;
+  BK_HIP(hipEventSynchronize(p->evs[last][4]));
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < p->ev_count; ++j) {
+    const int set = (last + K - j) % K;
+    for (int i = 0; i < 4; ++i) {
+      float t = 0.f;
+      BK_HIP(hipEventElapsedTime(&t, p->evs[set][i], p->evs[set][i + 1]));
+      acc[i] += double(t);
+    }
   }
+  for (int i = 0; i < 4; ++i) ms[i] = acc[i] / p->ev_count;
+  if (cap > 4) ms[4] = double(p->ev_count);
   return BK_OK;
 }
 
 bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes, size_t* needed) {
   g_last_error.clear();
   if (!p) return fail(BK_ERR_ARG, "null plan");
-  const size_t cs = 2 * p->elem;
-  const size_t n2 = size_t(p->sh.n) * p->sh.n;
   size_t bytes = 0;
   const void* src = nullptr;
   std::vector<int32_t> table;
-  if (which == 0) {
-    bytes = size_t(p->batch) * p->nkeep * n2 * cs;
-    src = p->d_F;
-  } else if (which == 1) {
-    bytes = size_t(p->batch) * size_t(p->tab.d_elems) * cs;
-    src = p->d_D;
+  if (which == 0 || which == 1 || which == 6) {
+    device_buffer(p, which, &src, &bytes);
   } else if (which == 2) {
     for (size_t g = 0; g < p->tab.gside_side.size(); ++g) {
       const int32_t s = p->tab.gside_side[g];
@@ -887,7 +1054,7 @@ bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes,
   } else if (which == 5) {
     bytes = p->tab.group_sides.size() * sizeof(int32_t);
   } else {
-    return fail(BK_ERR_ARG, "which must be 0..5");
+    return fail(BK_ERR_ARG, "which must be 0..6");
   }
   if (needed) *needed = bytes;
   if (!out) return BK_OK;
@@ -896,7 +1063,7 @@ bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes,
     std::memcpy(out, table.data(), bytes);
     return BK_OK;
   }
-  if (which >= 3) {
+  if (which >= 3 && which <= 5) {
     const void* hs = which == 3 ? static_cast<const void*>(p->tab.items.data())
                      : which == 4 ? static_cast<const void*>(p->tab.groups.data())
                                   : static_cast<const void*>(p->tab.group_sides.data());
@@ -907,6 +1074,38 @@ bk_status bk_debug_get_buffer(bk_plan p, int which, void* out, size_t cap_bytes,
   BK_HIP(hipSetDevice(p->device));
   BK_HIP(hipStreamSynchronize(p->stream));
   BK_HIP(hipMemcpy(out, src, bytes, hipMemcpyDeviceToHost));
+  return BK_OK;
+}
+
+bk_status bk_debug_read_range(bk_plan p, int which, size_t offset_bytes, void* out, size_t bytes) {
+  g_last_error.clear();
+  if (!p || (!out && bytes)) return fail(BK_ERR_ARG, "null argument");
+  if (which != 0 && which != 1 && which != 6) return fail(BK_ERR_ARG, "which must be 0, 1 or 6");
+  const void* src = nullptr;
+  size_t total = 0;
+  device_buffer(p, which, &src, &total);
+  if (offset_bytes > total || bytes > total - offset_bytes) return fail(BK_ERR_SIZE, "range outside the buffer");
+  if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run");
+  if (bytes == 0) return BK_OK;
+  BK_HIP(hipSetDevice(p->device));
+  BK_HIP(hipStreamSynchronize(p->stream));
+  BK_HIP(hipMemcpy(out, static_cast<const char*>(src) + offset_bytes, bytes, hipMemcpyDeviceToHost));
+  return BK_OK;
+}
+
+bk_status bk_debug_set_D(bk_plan p, const void* D, int batch, int is_device_ptr, void* hip_stream) {
+  g_last_error.clear();
+  if (!p || !D) return fail(BK_ERR_ARG, "null argument");
+  if (batch < 1 || batch > p->max_batch) return fail(BK_ERR_ARG, "batch must be in [1, max_batch]");
+  BK_HIP(hipSetDevice(p->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t bytes = size_t(batch) * size_t(p->tab.d_elems) * 2 * p->elem;
+  BK_HIP(hipMemcpyAsync(p->d_D, D, bytes, is_device_ptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (!is_device_ptr) BK_HIP(hipStreamSynchronize(st));
+  p->batch = batch;
+  p->estimated = 0;
+  p->d_injected = 1;
+  p->stream = st;
   return BK_OK;
 }
 
@@ -972,7 +1171,9 @@ bk_status group_capture(bk_group g) {
     bk_plan p = g->plans[i];
     he = hipStreamWaitEvent(g->side[i], g->fork, 0);
     if (he != hipSuccess) break;
-    st = p->prec == BK_F32 ? launch_all<float>(p, g->side[i], false) : launch_all<double>(p, g->side[i], false);
+    Bufs bf = plan_bufs(p);
+    bf.skip_fft = false;
+    st = p->prec == BK_F32 ? launch_all<float>(p, bf, g->side[i], false) : launch_all<double>(p, bf, g->side[i], false);
     if (st != BK_OK) break;
     he = hipEventRecord(g->join[i], g->side[i]);
     if (he == hipSuccess) he = hipStreamWaitEvent(g->cap, g->join[i], 0);
@@ -1050,7 +1251,7 @@ bk_status bk_group_estimate(bk_group g, void* hip_stream) {
   for (auto p : g->plans) {
     p->stream = st;
     p->estimated = 1;
-    p->timed = 0;
+    p->ev_count = 0;
   }
   return BK_OK;
 }
@@ -1098,7 +1299,9 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
     p->k3_chunk = c_k3[std::min(i, c_k3.size() - 1)];
     p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->k3_chunk);
     for (int rep = 0; rep < 2; ++rep) {
-      bk_status sst = p->prec == BK_F32 ? launch_all<float>(p, st, true) : launch_all<double>(p, st, true);
+      Bufs bf = plan_bufs(p);
+      bf.skip_fft = false;
+      bk_status sst = timed_launch(p, bf, st);
       if (sst != BK_OK) {
         p->fft_tb = saved[0];
         p->k2_tb = saved[1];
@@ -1107,6 +1310,7 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
         return sst;
       }
     }
+    // p->ev still points at the set of the second run
     BK_HIP(hipEventSynchronize(p->ev[4]));
     float ms[3];
     for (int k = 0; k < 3; ++k) BK_HIP(hipEventElapsedTime(&ms[k], p->ev[k], p->ev[k + 1]));
@@ -1122,10 +1326,12 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
   p->k3_chunk = best(c_k3, t_k3);
   p->lds_k3 = k3_lds_bytes(p->tab, p->prec, p->k3_chunk);
   p->tuned = 1;
-  // the last configuration timed ran the whole path: its results stand
+  p->d_injected = 0;
+  // the last configuration timed ran the whole path: its results and stage
+  // times stand
   p->stream = st;
   p->estimated = 1;
-  p->timed = 1;
+  p->ev_count = 1;
   {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     g_tune_cache[tune_key(p)] = {p->fft_tb, p->k2_tb, p->k3_chunk};
@@ -1137,3 +1343,4 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
   }
   return BK_OK;
 }
+

@@ -1,8 +1,8 @@
 """Write oracle expected values for the full-size parity tests.
 
 Calls only the oracle (float64, CPU) and the seeded input generator:
-    python tests/golden/make_golden.py [ng ...]
-For each grid it stores, in tests/golden/oracle_ng<N>.npz: the multipoles
+    python tests/golden/make_golden.py [name ...]
+For each workload it stores, in tests/golden/oracle_<name>.npz: the multipoles
 B [n_lm][n_k1][n_mu][n_t] (NaN where empty), the triangle counts, the (l, m)
 list, the binning and recipe, and the SHA-256 of the generated field so a test
 can confirm it regenerated the same input.
@@ -20,32 +20,39 @@ from oracle.estimator import estimate_streaming  # noqa: E402
 from oracle.geometry import Binning  # noqa: E402
 from synth import FieldRecipe, field_digest, make_field  # noqa: E402
 
-# The two single-realisation workloads: N_g = 128 (20 k1 x 10 mu x 10 t) and
-# N_g = 256 (40 k1 x 20 mu x 10 t); field: P ~ k^-2, f_NG = 0.5, beta = 0.5, seed 0.
+# Single-realisation workloads; field P ~ k^-2, f_NG = 0.5, beta = 0.5:
+#   ng128, ng256  N_g = 128 (20 k1 x 10 mu x 10 t) and 256 (40 k1 x 20 mu x 10 t), seed 0
+#   ng128_all_l   the N_g = 128 workload with every l <= 6 (odd l from the imaginary part)
+#   ng96          the first N_g = 96 field of the uneven batch (seed 24; 20 k1 on [1, 32), 10 x 10)
+#   ng192         N_g = 192, 20 k1 shells on [1, 64), 10 mu x 10 t, seed 0
 CONFIGS = {
-    128: (Binning(128, 20, 1.0, 128 / 3, 10, 10), FieldRecipe(128, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
-    256: (Binning(256, 40, 1.0, 256 / 3, 20, 10), FieldRecipe(256, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
+    "ng128": (Binning(128, 20, 1.0, 128 / 3, 10, 10), FieldRecipe(128, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
+    "ng256": (Binning(256, 40, 1.0, 256 / 3, 20, 10), FieldRecipe(256, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
+    "ng128_all_l": (Binning(128, 20, 1.0, 128 / 3, 10, 10, even_l_only=False),
+                    FieldRecipe(128, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
+    "ng96": (Binning(96, 20, 1.0, 32.0, 10, 10), FieldRecipe(96, n_s=-2.0, f_ng=0.5, beta=0.5, seed=24)),
+    "ng192": (Binning(192, 20, 1.0, 64.0, 10, 10), FieldRecipe(192, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
 }
 
 
-def main(ngs):
-    for ng in ngs:
-        b, rec = CONFIGS[ng]
+def main(names):
+    for name in names:
+        b, rec = CONFIGS[name]
         t0 = time.time()
         delta = make_field(rec)
         res = estimate_streaming(delta, b, workers=int(os.environ.get("ORACLE_WORKERS", "8")), chunks=256)
-        out = os.path.join(HERE, f"oracle_ng{ng}.npz")
+        out = os.path.join(HERE, f"oracle_{name}.npz")
         np.savez_compressed(
             out,
             B=res.B,
             counts=res.counts,
             lms=np.array(res.lms),
-            binning=np.array([b.ng, b.n_k1, b.k1_min, b.k1_max, b.n_mu, b.n_t]),
+            binning=np.array([b.ng, b.n_k1, b.k1_min, b.k1_max, b.n_mu, b.n_t, int(b.even_l_only)]),
             recipe=np.array([rec.ng, rec.n_s, rec.f_ng, rec.beta, rec.sigma_g, rec.seed]),
             digest=np.array(field_digest(delta)),
         )
-        print(f"ng={ng}: wrote {out} in {time.time() - t0:.0f} s", flush=True)
+        print(f"{name}: wrote {out} in {time.time() - t0:.0f} s", flush=True)
 
 
 if __name__ == "__main__":
-    main([int(a) for a in sys.argv[1:]] or [128, 256])
+    main(sys.argv[1:] or ["ng128", "ng256"])
