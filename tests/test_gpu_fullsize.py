@@ -111,54 +111,3 @@ def test_fullsize_every_l(ng, prec):
         worst = max(worst, np.max(np.abs(Bf[j][okj] + B[j][okj])) / scale)
     print(f"  odd-l reflection residual {worst:.3e}", flush=True)
     assert worst < tol
-
-
-@pytest.mark.timeout(900)
-def test_ng512_properties():
-    """N_g = 512, the largest configuration (60 k1 x 20 mu x 15 t bins, every
-    l <= 6), in bench.py's launch configuration.  No oracle run fits this size,
-    so properties that hold at any size: the float32 path agrees with the
-    float64 path to the float32 bar, and under a z reflection of the field the
-    float64 path keeps every even l and negates every odd l."""
-    import torch
-
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_2405_14513_amd import bk
-    from synth import make_field_torch
-
-    ng = 512
-    print("N_g = 512 properties: building plans", flush=True)
-    binning = bk.make_binning(ng, 60, 1.0, ng / 3, 20, 15, even_l_only=0)
-    field = make_field_torch(FieldRecipe(ng, n_s=-1.5, f_ng=0.5, beta=0.5, seed=7))
-    flip = torch.roll(torch.flip(field, dims=[2]), 1, dims=2).contiguous()
-    s = torch.cuda.current_stream().cuda_stream
-    res = {}
-    for prec in (2, 1):
-        est = bk.Estimator(binning, prec=prec)
-        print(f"  precision {prec}: plan built", flush=True)
-        try:
-            for name, f in (("field", field), ("flip", flip)) if prec == 2 else (("field", field),):
-                est.load(f if prec == 2 else f.to(torch.float32).contiguous(), s)
-                est.estimate(s)
-                res[(prec, name)] = est.multipoles()[0]
-            lms = est.lm_list()
-        finally:
-            est.close()
-        print(f"  precision {prec} done", flush=True)
-    del field, flip
-    B64, B32, Bf = res[(2, "field")], res[(1, "field")], res[(2, "flip")]
-    nlm = len(lms)
-    B64, B32, Bf = B64.reshape(nlm, -1), B32.reshape(nlm, -1), Bf.reshape(nlm, -1)
-    assert np.array_equal(np.isnan(B64), np.isnan(B32)) and np.array_equal(np.isnan(B64), np.isnan(Bf))
-    worst32, worst_flip = 0.0, 0.0
-    for j, (l, _) in enumerate(lms):
-        ok = ~np.isnan(B64[j])
-        scale = np.max(np.abs(B64[j][ok]))
-        assert scale > 0, lms[j]
-        worst32 = max(worst32, np.max(np.abs(B32[j][ok] - B64[j][ok])) / scale)
-        sign = -1.0 if l % 2 else 1.0
-        worst_flip = max(worst_flip, np.max(np.abs(Bf[j][ok] - sign * B64[j][ok])) / scale)
-    print(f"  float32 vs float64 {worst32:.3e}, z reflection {worst_flip:.3e}", flush=True)
-    assert worst32 < 1e-5
-    assert worst_flip < 1e-11

@@ -8,10 +8,13 @@ workloads (N_g = 96, 192, 384, 512), and of the test-support entry points.
   float64 library FFT of the same field, and D (Eq. 9) of sampled grid sides
   of every grid level against the ring's modes folded onto that grid and
   transformed by the library FFT.
-* Contraction cells at full size: S = sum over the item's grid of
-  D_A D_B conj(D_C) (Eq. 8 on the reduced grid) of sampled work items of
-  every grid level, against float64 sums of the library's own D (the
-  contraction alone) and of the reference D (ring sums and contraction).
+* Contraction cells at full size (N_g = 256, 384, 512): S = sum over the
+  item's grid of D_A D_B conj(D_C) (Eq. 8 on the reduced grid) of sampled
+  work items of every grid level, against float64 sums of the library's own
+  D (the contraction alone) and of the reference D (ring sums and
+  contraction).
+* N_g = 512 binned outputs, which no oracle run reaches, by properties: the
+  float32 path against the float64 path, and the z reflection.
 * D set directly (bk_debug_set_D): the contraction and binning alone on ring
   sums computed here, against the oracle.
 * The graph-replayed estimate against the kernel-by-kernel one, bit for bit.
@@ -123,11 +126,61 @@ SIZES = {  # binning of each size: the workloads' own
 }
 
 
+def _device_spectrum(torch, field, prec):
+    """float64 library FFT of the (rounded) input field, in the plan's units (N^-3/2 DFT)."""
+    ng = field.shape[0]
+    x = field if prec == 2 else field.to(torch.float32).to(torch.float64)
+    return torch.fft.fftn(x) * ng ** -1.5
+
+
+def _load_estimate(torch, est, field, prec):
+    s = torch.cuda.current_stream().cuda_stream
+    est.load(field if prec == 2 else field.to(torch.float32).contiguous(), s)
+    est.estimate(s)
+    torch.cuda.synchronize()
+
+
+def _check_stage_buffers(torch, bk, est, Dft, prec):
+    """Delta planes (K1) and D of sampled grid sides of every grid level (K2)
+    of the last estimate against the library-FFT references."""
+    ng = Dft.shape[0]
+    tol = 1e-13 if prec == 2 else 1e-5
+    n2 = ng * ng
+    nplanes = bk.bk_debug_get_buffer_size(est.plan, 0) // (n2 * (8 if prec == 1 else 16))
+    worst_f = 0.0
+    for n in range(nplanes):
+        F = torch.from_numpy(bk.bk_debug_read_range(est.plan, 0, prec, n * n2, n2).astype(np.complex128))
+        ref = Dft[:, :, n].cpu()
+        worst_f = max(worst_f, float((F.reshape(ng, ng) - ref).abs().max() / ref.abs().max()))
+    _say(f"  Delta planes: {nplanes}, worst error {worst_f:.2e}")
+    assert worst_f < tol
+    tab = bk.bk_debug_get_buffer(est.plan, 2, prec).reshape(-1, 3).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(tab[:, 2] ** 2)])
+    rings = _rings(ng)
+    levels = sorted(set(tab[:, 2].tolist()))
+    _say(f"  grid levels {levels}")
+    if ng >= 384:
+        assert {256, 320, ng} <= set(levels)
+    worst_d = 0.0
+    for m in levels:
+        idx = np.flatnonzero(tab[:, 2] == m)
+        pick = sorted(set([idx[0], idx[len(idx) // 2], idx[-1], idx[np.argmax(tab[idx, 0])]]))
+        for g in pick:
+            r, n, _ = tab[g]
+            Dg = bk.bk_debug_read_range(est.plan, 1, prec, int(offs[g]), int(m * m)).astype(np.complex128)
+            ref = _reference_D(torch, Dft, rings.modes[r - 1], int(n), int(m)).cpu().numpy().ravel()
+            e = np.abs(Dg - ref).max() / np.abs(ref).max()
+            worst_d = max(worst_d, e)
+            assert e < tol, (r, n, m, e)
+    _say(f"  D of sampled grid sides: worst error {worst_d:.2e}")
+
+
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("ng,prec", [(96, 2), (96, 1), (192, 2), (192, 1), (384, 2), (384, 1), (512, 1)],
-                         ids=["ng96-f64", "ng96-f32", "ng192-f64", "ng192-f32", "ng384-f64", "ng384-f32", "ng512-f32"])
+@pytest.mark.parametrize("ng,prec", [(96, 2), (96, 1), (192, 2), (192, 1), (384, 2)],
+                         ids=["ng96-f64", "ng96-f32", "ng192-f64", "ng192-f32", "ng384-f64"])
 def test_stage_buffers_every_size(ng, prec):
-    """Delta planes (K1) and D of sampled grid sides of every grid level (K2)."""
+    """Delta planes (K1) and D of sampled grid sides of every grid level (K2);
+    N_g = 384 in float32 and 512 are checked with their contraction cells below."""
     torch = _torch()
     from paper_2405_14513_amd import bk
 
@@ -135,44 +188,8 @@ def test_stage_buffers_every_size(ng, prec):
     field = _field_on_device(torch, ng, seed=31)
     est = bk.Estimator(bk.make_binning(ng, *SIZES[ng]), prec=prec)
     try:
-        s = torch.cuda.current_stream().cuda_stream
-        est.load(field if prec == 2 else field.to(torch.float32).contiguous(), s)
-        est.estimate(s)
-        torch.cuda.synchronize()
-        _say("  estimate done; comparing")
-        scale = ng ** -1.5
-        x = field if prec == 2 else field.to(torch.float32).to(torch.float64)
-        Dft = torch.fft.fftn(x) * scale  # float64 library FFT of the same (rounded) input
-        del x
-        tol = 1e-13 if prec == 2 else 1e-5
-        n2 = ng * ng
-        nplanes = bk.bk_debug_get_buffer_size(est.plan, 0) // (n2 * (8 if prec == 1 else 16))
-        worst_f = 0.0
-        for n in range(nplanes):
-            F = torch.from_numpy(bk.bk_debug_read_range(est.plan, 0, prec, n * n2, n2).astype(np.complex128))
-            ref = Dft[:, :, n].cpu()
-            worst_f = max(worst_f, float((F.reshape(ng, ng) - ref).abs().max() / ref.abs().max()))
-        _say(f"  Delta planes: {nplanes}, worst error {worst_f:.2e}")
-        assert worst_f < tol
-        tab = bk.bk_debug_get_buffer(est.plan, 2, prec).reshape(-1, 3).astype(np.int64)
-        offs = np.concatenate([[0], np.cumsum(tab[:, 2] ** 2)])
-        rings = _rings(ng)
-        levels = sorted(set(tab[:, 2].tolist()))
-        _say(f"  grid levels {levels}")
-        if ng >= 384:
-            assert {256, 320, ng} <= set(levels)
-        worst_d = 0.0
-        for m in levels:
-            idx = np.flatnonzero(tab[:, 2] == m)
-            pick = sorted(set([idx[0], idx[len(idx) // 2], idx[-1], idx[np.argmax(tab[idx, 0])]]))
-            for g in pick:
-                r, n, _ = tab[g]
-                Dg = bk.bk_debug_read_range(est.plan, 1, prec, int(offs[g]), int(m * m)).astype(np.complex128)
-                ref = _reference_D(torch, Dft, rings.modes[r - 1], int(n), int(m)).cpu().numpy().ravel()
-                e = np.abs(Dg - ref).max() / np.abs(ref).max()
-                worst_d = max(worst_d, e)
-                assert e < tol, (r, n, m, e)
-        _say(f"  D of sampled grid sides: worst error {worst_d:.2e}")
+        _load_estimate(torch, est, field, prec)
+        _check_stage_buffers(torch, bk, est, _device_spectrum(torch, field, prec), prec)
     finally:
         est.close()
 
@@ -188,94 +205,168 @@ def _decode(bk, plan, prec):
     return groups, items, gsides, tab
 
 
-@pytest.mark.timeout(600)
-@pytest.mark.parametrize("ng,prec,even", [(256, 1, 1), (256, 2, 1), (384, 1, 0), (512, 1, 0)],
-                         ids=["ng256-f32", "ng256-f64", "ng384-f32-all-l", "ng512-f32-all-l"])
-def test_contraction_cells_fullsize(ng, prec, even):
+def _check_cells(torch, bk, est, Dft, prec, even):
     """Re S (and Im S for every-l plans) of sampled work items of every grid
-    level: against float64 sums of the library's own D (the contraction alone,
-    tight bar) and of reference D from the library FFT (loose bar)."""
+    level of the last estimate: against float64 sums of the library's own D
+    (the contraction alone, tight bar) and of the reference D (loose bar).
+    The bar is relative to the first-order error bound of S from per-side
+    relative errors of D."""
+    ng = Dft.shape[0]
+    groups, items, gsides, tab = _decode(bk, est.plan, prec)
+    offs = np.concatenate([[0], np.cumsum(tab[:, 2] ** 2)])
+    cells = 512 if even == 0 else 256
+    rings = _rings(ng)
+    rng = np.random.default_rng(5)
+    by_grid = {}
+    for gi, gd in enumerate(groups):
+        by_grid.setdefault(int(gd[5]), []).append(gi)
+    cache_gpu, cache_ref = {}, {}
+
+    def side_pair(g):
+        if g not in cache_gpu:
+            r, n, m = tab[g]
+            Dg = bk.bk_debug_read_range(est.plan, 1, prec, int(offs[g]), int(m * m)).astype(np.complex128)
+            cache_gpu[g] = torch.from_numpy(Dg).cuda()
+            cache_ref[g] = _reference_D(torch, Dft, rings.modes[r - 1], int(n), int(m)).reshape(-1)
+        return cache_gpu[g], cache_ref[g]
+
+    worst_own, worst_ref, checked = 0.0, 0.0, 0
+    for m, gl in sorted(by_grid.items()):
+        for gi in rng.choice(gl, size=min(2, len(gl)), replace=False):
+            gd = groups[gi]
+            side_begin, n_sides, item_begin, n_items = (int(v) for v in gd[:4])
+            for it in rng.choice(n_items, size=min(2, n_items), replace=False):
+                item = item_begin + int(it)
+                desc = items[item]
+                S = bk.bk_debug_read_range(est.plan, 6, prec, item * cells, cells)
+                zero = torch.zeros(m * m, dtype=torch.complex128, device="cuda")
+
+                def D_of(slot):
+                    if slot == n_sides:
+                        return zero, zero
+                    return side_pair(int(gsides[side_begin + slot]) & 0xFFFFFF)
+
+                A = [D_of(int(v)) for v in desc[0:16]]
+                C = [D_of(int(v)) for v in desc[64:80]]
+                Bs = [D_of(int(v)) for v in desc[128:144]]
+                for k in (0, 1):  # 0: the library's own D, 1: reference D
+                    PA = torch.stack([a[k] * torch.conj(c[k]) for a, c in zip(A, C)])
+                    DB = torch.stack([b[k] for b in Bs])
+                    Sref = (PA @ DB.transpose(0, 1).contiguous()).cpu().numpy()  # [pair][column]
+                    # first-order bound of the error from per-side relative errors of D
+                    aA = torch.stack([a[k].abs() for a in A])
+                    aC = torch.stack([c[k].abs() for c in C])
+                    aB = torch.stack([b[k].abs() for b in Bs])
+                    mA, mC, mB = (t.max(dim=1).values for t in (aA, aC, aB))
+                    bound = (mA[:, None] * (aC @ aB.T) + mC[:, None] * (aA @ aB.T)
+                             + mB[None, :] * (aA * aC).sum(dim=1)[:, None]).cpu().numpy()
+                    got = S[:256].reshape(16, 16)
+                    e_re = np.max(np.abs(got - Sref.real) / np.maximum(bound, 1e-300))
+                    e = e_re
+                    if even == 0:
+                        got_im = S[256:512].reshape(16, 16)
+                        e = max(e, np.max(np.abs(got_im - Sref.imag) / np.maximum(bound, 1e-300)))
+                    if k == 0:
+                        worst_own = max(worst_own, float(e))
+                    else:
+                        worst_ref = max(worst_ref, float(e))
+                checked += 1
+    _say(f"  {checked} items over grids {sorted(by_grid)}: contraction alone {worst_own:.2e}, "
+         f"with reference D {worst_ref:.2e}")
+    assert checked >= 2 * len(by_grid)
+    assert worst_own < (1e-12 if prec == 2 else 1e-5)
+    assert worst_ref < (1e-11 if prec == 2 else 1e-4)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [1, 2], ids=["f32", "f64"])
+def test_contraction_cells_ng256(prec):
     torch = _torch()
     from paper_2405_14513_amd import bk
 
-    _say(f"contraction cells ng={ng} prec={prec} even_l_only={even}: building the plan")
-    field = _field_on_device(torch, ng, seed=41)
-    est = bk.Estimator(bk.make_binning(ng, *SIZES.get(ng, (40, 1.0, ng / 3, 20, 10)), even_l_only=even), prec=prec)
+    _say(f"contraction cells ng=256 prec={prec}: building the plan")
+    field = _field_on_device(torch, 256, seed=41)
+    est = bk.Estimator(bk.make_binning(256, 40, 1.0, 256 / 3, 20, 10), prec=prec)
     try:
-        s = torch.cuda.current_stream().cuda_stream
-        est.load(field if prec == 2 else field.to(torch.float32).contiguous(), s)
-        est.estimate(s)
-        torch.cuda.synchronize()
-        _say("  estimate done; sampling items")
-        x = field if prec == 2 else field.to(torch.float32).to(torch.float64)
-        Dft = torch.fft.fftn(x) * ng ** -1.5
-        del x
-        groups, items, gsides, tab = _decode(bk, est.plan, prec)
-        offs = np.concatenate([[0], np.cumsum(tab[:, 2] ** 2)])
-        cells = 512 if even == 0 else 256
-        rings = _rings(ng)
-        rng = np.random.default_rng(5)
-        by_grid = {}
-        for gi, gd in enumerate(groups):
-            by_grid.setdefault(int(gd[5]), []).append(gi)
-        cache_gpu, cache_ref = {}, {}
-
-        def side_pair(g):
-            if g not in cache_gpu:
-                r, n, m = tab[g]
-                Dg = bk.bk_debug_read_range(est.plan, 1, prec, int(offs[g]), int(m * m)).astype(np.complex128)
-                cache_gpu[g] = torch.from_numpy(Dg).cuda()
-                cache_ref[g] = _reference_D(torch, Dft, rings.modes[r - 1], int(n), int(m)).reshape(-1)
-            return cache_gpu[g], cache_ref[g]
-
-        worst_own, worst_ref, checked = 0.0, 0.0, 0
-        for m, gl in sorted(by_grid.items()):
-            for gi in rng.choice(gl, size=min(2, len(gl)), replace=False):
-                gd = groups[gi]
-                side_begin, n_sides, item_begin, n_items = (int(v) for v in gd[:4])
-                for it in rng.choice(n_items, size=min(2, n_items), replace=False):
-                    item = item_begin + int(it)
-                    desc = items[item]
-                    S = bk.bk_debug_read_range(est.plan, 6, prec, item * cells, cells)
-                    zero = torch.zeros(m * m, dtype=torch.complex128, device="cuda")
-
-                    def D_of(slot):
-                        if slot == n_sides:
-                            return zero, zero
-                        return side_pair(int(gsides[side_begin + slot]) & 0xFFFFFF)
-
-                    A = [D_of(int(v)) for v in desc[0:16]]
-                    C = [D_of(int(v)) for v in desc[64:80]]
-                    Bs = [D_of(int(v)) for v in desc[128:144]]
-                    for k, worst in ((0, "own"), (1, "ref")):
-                        PA = torch.stack([a[k] * torch.conj(c[k]) for a, c in zip(A, C)])
-                        DB = torch.stack([b[k] for b in Bs])
-                        Sref = (PA @ DB.transpose(0, 1).contiguous()).cpu().numpy()  # [pair][column]
-                        # first-order bound of the error from per-side relative errors of D
-                        aA = torch.stack([a[k].abs() for a in A])
-                        aC = torch.stack([c[k].abs() for c in C])
-                        aB = torch.stack([b[k].abs() for b in Bs])
-                        mA, mC, mB = (t.max(dim=1).values for t in (aA, aC, aB))
-                        bound = (mA[:, None] * (aC @ aB.T) + mC[:, None] * (aA @ aB.T)
-                                 + mB[None, :] * (aA * aC).sum(dim=1)[:, None]).cpu().numpy()
-                        got = S[:256].reshape(16, 16)
-                        e_re = np.max(np.abs(got - Sref.real) / np.maximum(bound, 1e-300))
-                        e = e_re
-                        if even == 0:
-                            got_im = S[256:512].reshape(16, 16)
-                            e = max(e, np.max(np.abs(got_im - Sref.imag) / np.maximum(bound, 1e-300)))
-                        if k == 0:
-                            worst_own = max(worst_own, float(e))
-                        else:
-                            worst_ref = max(worst_ref, float(e))
-                    checked += 1
-        _say(f"  {checked} items over grids {sorted(by_grid)}: contraction alone {worst_own:.2e}, "
-             f"with reference D {worst_ref:.2e}")
-        assert checked >= 2 * len(by_grid)
-        assert worst_own < (1e-12 if prec == 2 else 1e-5)
-        assert worst_ref < (1e-11 if prec == 2 else 1e-4)
+        _load_estimate(torch, est, field, prec)
+        _check_cells(torch, bk, est, _device_spectrum(torch, field, prec), prec, 1)
     finally:
         est.close()
+
+
+@pytest.mark.timeout(600)
+def test_ng384_float32_every_l():
+    """The paper's grid size in float32 with every l: stage buffers and contraction cells."""
+    torch = _torch()
+    from paper_2405_14513_amd import bk
+
+    _say("ng=384 float32 every l: building the plan")
+    field = _field_on_device(torch, 384, seed=41)
+    est = bk.Estimator(bk.make_binning(384, *SIZES[384], even_l_only=0), prec=1)
+    try:
+        _load_estimate(torch, est, field, 1)
+        Dft = _device_spectrum(torch, field, 1)
+        _check_stage_buffers(torch, bk, est, Dft, 1)
+        _check_cells(torch, bk, est, Dft, 1, 0)
+    finally:
+        est.close()
+
+
+@pytest.mark.timeout(900)
+def test_ng512():
+    """N_g = 512, the largest configuration (60 k1 x 20 mu x 15 t bins, every
+    l <= 6), in bench.py's launch configuration.  Float32 plan: stage buffers
+    and contraction cells against the library-FFT references.  No oracle run
+    fits this size for the binned outputs, so properties that hold at any
+    size: the float32 path agrees with the float64 path to the float32 bar,
+    and under a z reflection of the field the float64 path keeps every even l
+    and negates every odd l."""
+    torch = _torch()
+    from paper_2405_14513_amd import bk
+
+    ng = 512
+    binning = bk.make_binning(ng, *SIZES[ng], even_l_only=0)
+    field = _field_on_device(torch, ng, seed=7)
+    s = torch.cuda.current_stream().cuda_stream
+    res = {}
+    _say("ng=512: float32 plan")
+    est = bk.Estimator(binning, prec=1)
+    try:
+        _load_estimate(torch, est, field, 1)
+        res[(1, "field")] = est.multipoles()[0]
+        Dft = _device_spectrum(torch, field, 1)
+        _check_stage_buffers(torch, bk, est, Dft, 1)
+        _check_cells(torch, bk, est, Dft, 1, 0)
+        del Dft
+        lms = est.lm_list()
+    finally:
+        est.close()
+    _say("ng=512: float64 plan")
+    flip = torch.roll(torch.flip(field, dims=[2]), 1, dims=2).contiguous()
+    est = bk.Estimator(binning, prec=2)
+    try:
+        for name, f in (("field", field), ("flip", flip)):
+            est.load(f, s)
+            est.estimate(s)
+            res[(2, name)] = est.multipoles()[0]
+    finally:
+        est.close()
+    del field, flip
+    B64, B32, Bf = res[(2, "field")], res[(1, "field")], res[(2, "flip")]
+    nlm = len(lms)
+    B64, B32, Bf = B64.reshape(nlm, -1), B32.reshape(nlm, -1), Bf.reshape(nlm, -1)
+    assert np.array_equal(np.isnan(B64), np.isnan(B32)) and np.array_equal(np.isnan(B64), np.isnan(Bf))
+    worst32, worst_flip = 0.0, 0.0
+    for j, (l, _) in enumerate(lms):
+        ok = ~np.isnan(B64[j])
+        scale = np.max(np.abs(B64[j][ok]))
+        assert scale > 0, lms[j]
+        worst32 = max(worst32, np.max(np.abs(B32[j][ok] - B64[j][ok])) / scale)
+        sign = -1.0 if l % 2 else 1.0
+        worst_flip = max(worst_flip, np.max(np.abs(Bf[j][ok] - sign * B64[j][ok])) / scale)
+    _say(f"  float32 vs float64 {worst32:.3e}, z reflection {worst_flip:.3e}")
+    assert worst32 < 1e-5
+    assert worst_flip < 1e-11
 
 
 # --- D set directly --------------------------------------------------------------
