@@ -274,6 +274,26 @@ bk_status bk_debug_set_D(bk_plan plan, const void* D, int batch, int is_device_p
  * the lane layout the contraction kernel assumes. */
 bk_status bk_debug_mfma_probe(int prec, double* out, size_t cap);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * estimate of bk_estimate for `batch` fields delta (a device pointer, C order
+ * [batch][x][y][z], dtype BK_F32 or BK_F64) into B_out (a device pointer to
+ * float64 [batch][n_lm][n_k1][n_mu][n_t], the layout of bk_get_multipoles).
+ * The plan supplies its geometry tables (allocated at bk_plan_create); the
+ * Delta planes, ring sums, contraction outputs and binning partials live in a
+ * static device array of the library, 64 MiB per device (enough for one
+ * N_g = 64 field in float64, two in float32), held by each device the library
+ * runs on until the process ends.  The call allocates nothing, enqueues the
+ * kernels on hip_stream and returns; it does not touch the plan's loaded
+ * fields, results or stage times.  Errors: BK_ERR_ARG for null pointers, a
+ * bad dtype or batch < 1; BK_ERR_SIZE (nothing launched) if the plan's
+ * working set for `batch` fields exceeds the array.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device (on
+ * different streams or host threads) race and must be serialised by the
+ * caller; consecutive calls on one stream are ordered and safe. */
+bk_status bk_estimate_noalloc(bk_plan plan, const void* delta, int dtype, int batch, double* B_out,
+                              void* hip_stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* bk_last_error(void);
 

@@ -68,6 +68,8 @@ _SIGS = {
     "bk_load_grid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "bk_estimate": [ctypes.c_void_p, ctypes.c_void_p],
     "bk_estimate_timed": [ctypes.c_void_p, ctypes.c_void_p],
+    "bk_estimate_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_void_p],
     "bk_synchronize": [ctypes.c_void_p],
     "bk_query_sizes": [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int)] * 4,
     "bk_get_lm_list": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_size_t],
@@ -146,6 +148,12 @@ def bk_estimate(plan: int, stream: int = 0):
 
 def bk_estimate_timed(plan: int, stream: int = 0):
     _check(lib().bk_estimate_timed(ctypes.c_void_p(plan), ctypes.c_void_p(stream)))
+
+
+def bk_estimate_noalloc(plan: int, ptr: int, dtype: int, batch: int, out_ptr: int, stream: int = 0):
+    """Estimate from device input `ptr` into device output `out_ptr` without allocating (static scratch)."""
+    _check(lib().bk_estimate_noalloc(ctypes.c_void_p(plan), ctypes.c_void_p(ptr), int(dtype), int(batch),
+                                     ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)))
 
 
 def bk_synchronize(plan: int):

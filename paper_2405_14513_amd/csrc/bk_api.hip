@@ -1344,3 +1344,78 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
   return BK_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free estimate
+// Working set of bk_estimate_noalloc: one array per device, in the library's
+// code object, that holds that call's Delta planes, ring sums D, contraction
+// outputs S and binning partials.  Host code never passes `scratch` itself to
+// a kernel (its host-side name is no device address); it takes the device's
+// address once from hipGetSymbolAddress and uses that.
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;
+}
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::map<int, void*> g_scratch_ptr;  // device -> device address of its `scratch`
+
+// The calling thread's current device must be `device`.
+bk_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return BK_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr)
+    return fail(BK_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = ptr;
+  *out = ptr;
+  return BK_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" bk_status bk_estimate_noalloc(bk_plan p, const void* delta, int dtype, int batch, double* B_out,
+                                         void* hip_stream) {
+  g_last_error.clear();
+  if (!p || !delta || !B_out) return fail(BK_ERR_ARG, "null argument");
+  if (dtype != BK_F32 && dtype != BK_F64) return fail(BK_ERR_ARG, "dtype must be BK_F32 or BK_F64");
+  if (batch < 1) return fail(BK_ERR_ARG, "batch must be >= 1");
+  const size_t cs = 2 * p->elem;
+  const size_t b = size_t(batch);
+  const size_t n2 = size_t(p->sh.n) * p->sh.n;
+  const size_t nlm = p->tab.lm_l.size();
+  const size_t f_bytes = align256(b * p->nkeep * n2 * cs);
+  const size_t d_bytes = align256(b * size_t(p->tab.d_elems) * cs);
+  const size_t s_bytes = align256(b * size_t(p->n_items) * size_t(p->item_out) * sizeof(double));
+  const size_t part_bytes = align256(b * size_t(std::max(1L, p->n_chunks)) * nlm * sizeof(double));
+  const size_t need = f_bytes + d_bytes + s_bytes + part_bytes;
+  if (need > kScratchBytes)
+    return fail(BK_ERR_SIZE, "this plan needs " + std::to_string(need) + " bytes of scratch for " +
+                                 std::to_string(batch) + " field(s); the allocation-free path holds " +
+                                 std::to_string(kScratchBytes));
+  BK_HIP(hipSetDevice(p->device));
+  void* base = nullptr;
+  bk_status st = scratch_address(p->device, &base);
+  if (st != BK_OK) return st;
+  char* c = static_cast<char*>(base);
+  Bufs bf;
+  bf.in = delta;
+  bf.in_dtype = dtype;
+  bf.batch = batch;
+  bf.F = c;
+  bf.D = c + f_bytes;
+  bf.S = reinterpret_cast<double*>(c + f_bytes + d_bytes);
+  bf.part = reinterpret_cast<double*>(c + f_bytes + d_bytes + s_bytes);
+  bf.B = B_out;
+  // every scratch element an estimate reads was written earlier in the same
+  // estimate, so nothing needs clearing between calls
+  hipStream_t hs = reinterpret_cast<hipStream_t>(hip_stream);
+  return p->prec == BK_F32 ? launch_all<float>(p, bf, hs, false) : launch_all<double>(p, bf, hs, false);
+}
