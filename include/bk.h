@@ -177,7 +177,7 @@ bk_status bk_get_stage_times(bk_plan plan, double* ms, size_t cap);
 
 /* Tile autotuning.  With a grid loaded, times every valid tile choice of the
  * three tiled stages on hip_stream (lines per block of the forward FFT 2..16,
- * columns per block of the ring sums 2..16, staged slots per chunk of the
+ * columns per block of the ring sums 4..16, staged slots per chunk of the
  * triple products 16..64, each within its LDS limit) and keeps the fastest of
  * each; the results do not depend on these choices beyond rounding order.
  * The choice is cached in the process per (N_g, precision, device, number of

@@ -238,13 +238,6 @@ size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
 // LDS of the FFT kernels: n twiddles plus two buffers of tb lines padded to n + 1.
 size_t fft_lds_bytes(int n, int tb, size_t elem_bytes) { return (size_t(n) + size_t(2) * tb * (n + 1)) * elem_bytes; }
 
-// The largest power of two <= want that divides m and keeps the FFT LDS within 72 KiB.
-int fit_tb(int m, int want, size_t elem_bytes) {
-  int tb = 1;
-  while (tb * 2 <= want && m % (tb * 2) == 0 && fft_lds_bytes(m, tb * 2, elem_bytes) <= 73728) tb *= 2;
-  return tb;
-}
-
 int pick_tb(int n, size_t elem_bytes) {
   // lines per block: at most 16, dividing n, LDS at most 72 KiB (two blocks per CU)
   int tb = 16;
@@ -318,6 +311,69 @@ void launch_k1(bk_plan p, const Bufs& bf, bk::cplx<T>* F, const bk::cplx<T>* tw,
   hipLaunchKernelGGL((bk::k_cols_kernel<T, N>), dim3(n / tb, B * p->nkeep), dim3(256), lds, st, F, tw, p->sh, tb);
 }
 
+// LDS of the ring sums: m twiddles plus one buffer of tb lines padded to m + 1.
+size_t k2_lds_bytes(int m, int tb, size_t elem_bytes) { return (size_t(m) + size_t(tb) * (m + 1)) * elem_bytes; }
+
+// Columns per block of the ring sums on an m-point grid: the largest of 16,
+// 8, 4 not above `want` that divides m and keeps the block's LDS within 40
+// KiB (four blocks per compute unit), 4 at least.
+int k2_slab(int m, int want, size_t elem_bytes) {
+  int tb = want >= 16 ? 16 : want >= 8 ? 8 : 4;
+  while (tb > 4 && (m % tb != 0 || k2_lds_bytes(m, tb, elem_bytes) > 40960)) tb /= 2;
+  return tb;
+}
+
+template <typename T, int M, int TB>
+void launch_k2_mt(bk_plan p, const Bufs& bf, const bk::cplx<T>* F, bk::cplx<T>* D, size_t L, int n_gs,
+                  const bk::cplx<T>* tw, hipStream_t st) {
+  if constexpr (M % TB == 0) {
+    dim3 g2(unsigned(n_gs) * (M / TB), bf.batch);
+    hipLaunchKernelGGL((bk::k2_ring_kernel<T, M, TB>), g2, dim3(bk::kK2Threads), k2_lds_bytes(M, TB, sizeof(bk::cplx<T>)), st,
+                       F, D, p->d_gs_side, p->d_gs_off, p->tab.level_gside_begin[L], long(p->tab.d_elems),
+                       p->d_side_ring, p->d_side_plane, p->d_side_u, p->d_ring_seg_off, p->d_ring_seg,
+                       p->d_ring_mode_uy, p->sh.n, p->nkeep, tw);
+  }
+}
+
+template <typename T, int M>
+void launch_k2_m(bk_plan p, const Bufs& bf, const bk::cplx<T>* F, bk::cplx<T>* D, size_t L, int tb, int n_gs,
+                 const bk::cplx<T>* tw, hipStream_t st) {
+  if (tb == 16)
+    launch_k2_mt<T, M, 16>(p, bf, F, D, L, n_gs, tw, st);
+  else if (tb == 8)
+    launch_k2_mt<T, M, 8>(p, bf, F, D, L, n_gs, tw, st);
+  else
+    launch_k2_mt<T, M, 4>(p, bf, F, D, L, n_gs, tw, st);
+}
+
+// The ring sums of grid level L (m points, slabs of tb columns); one kernel
+// instance per grid size the tables can produce.
+template <typename T>
+bk_status launch_k2(bk_plan p, const Bufs& bf, const bk::cplx<T>* F, bk::cplx<T>* D, size_t L, int m, int tb,
+                    int n_gs, const bk::cplx<T>* tw, hipStream_t st) {
+  if (m % tb != 0) return fail(BK_ERR_ARG, "internal: ring-sum slab does not divide the grid");
+  switch (m) {
+    case 8: launch_k2_m<T, 8>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 16: launch_k2_m<T, 16>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 24: launch_k2_m<T, 24>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 32: launch_k2_m<T, 32>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 40: launch_k2_m<T, 40>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 48: launch_k2_m<T, 48>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 64: launch_k2_m<T, 64>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 80: launch_k2_m<T, 80>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 96: launch_k2_m<T, 96>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 128: launch_k2_m<T, 128>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 160: launch_k2_m<T, 160>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 192: launch_k2_m<T, 192>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 256: launch_k2_m<T, 256>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 320: launch_k2_m<T, 320>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 384: launch_k2_m<T, 384>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    case 512: launch_k2_m<T, 512>(p, bf, F, D, L, tb, n_gs, tw, st); break;
+    default: return fail(BK_ERR_ARG, "internal: no ring-sum kernel for grid size " + std::to_string(m));
+  }
+  return BK_OK;
+}
+
 // K1 and K2: the forward FFT of the fields, then the ring sums D of every
 // grid side (ev[1] between them when timing).
 template <typename T>
@@ -349,7 +405,7 @@ bk_status launch_fft(bk_plan p, const Bufs& bf, hipStream_t st, bool timing) {
   }
   BK_HIP(hipGetLastError());
   if (timing) BK_HIP(hipEventRecord(p->ev[1], st));
-  // K2: ring sums, pruned row DFT + column FFT per (grid side, column block), one launch per grid level
+  // K2: ring sums, pruned row DFT + column FFT per (grid side, column slab), one launch per grid level
   {
     const C* twl = reinterpret_cast<const C*>(p->d_tw_lv);
     const auto& lvb = p->tab.level_gside_begin;
@@ -357,35 +413,9 @@ bk_status launch_fft(bk_plan p, const Bufs& bf, hipStream_t st, bool timing) {
       const int n_gs = lvb[L + 1] - lvb[L];
       if (n_gs == 0) continue;
       const int m = p->tab.grid_sizes[L];
-      // columns per block: 8 (float32) or 4 (float64) by default, i.e. 64-byte row segments
-      const int tb2 = fit_tb(m, p->k2_tb > 0 ? p->k2_tb : (prec_is_f32<T>() ? 8 : 4), cs);
-      dim3 g2(n_gs * (m / tb2), B);
-      const size_t lds2 = fft_lds_bytes(m, tb2, cs);
-      // one instance per grid size the tables can produce; any other size takes the runtime-length kernel
-#define BK_K2(MV)                                                                                                \
-  hipLaunchKernelGGL((bk::k2_fused_kernel<T, MV>), g2, dim3(256), lds2, st, F, D, p->d_gs_side, p->d_gs_off,     \
-                     lvb[L], long(p->tab.d_elems), p->d_side_ring, p->d_side_plane, p->d_side_u, p->d_ring_seg_off, \
-                     p->d_ring_seg, p->d_ring_mode_uy, n, p->nkeep, twl + p->tw_lv_off[L], p->lv_sh[L], tb2)
-      switch (m) {
-        case 8: BK_K2(8); break;
-        case 16: BK_K2(16); break;
-        case 24: BK_K2(24); break;
-        case 32: BK_K2(32); break;
-        case 40: BK_K2(40); break;
-        case 48: BK_K2(48); break;
-        case 64: BK_K2(64); break;
-        case 80: BK_K2(80); break;
-        case 96: BK_K2(96); break;
-        case 128: BK_K2(128); break;
-        case 160: BK_K2(160); break;
-        case 192: BK_K2(192); break;
-        case 256: BK_K2(256); break;
-        case 320: BK_K2(320); break;
-        case 384: BK_K2(384); break;
-        case 512: BK_K2(512); break;
-        default: BK_K2(0);
-      }
-#undef BK_K2
+      const int tb2 = k2_slab(m, p->k2_tb > 0 ? p->k2_tb : 16, cs);
+      bk_status s2 = launch_k2<T>(p, bf, F, D, L, m, tb2, n_gs, twl + p->tw_lv_off[L], st);
+      if (s2 != BK_OK) return s2;
       BK_HIP(hipGetLastError());
     }
   }
@@ -1279,10 +1309,8 @@ extern "C" bk_status bk_plan_autotune(bk_plan p, void* hip_stream, int* choices)
   const size_t cs = 2 * p->elem;
   std::vector<int> c_fft, c_k2, c_k3;
   for (int tb : {2, 4, 8, 16})
-    if (n % tb == 0 && fft_lds_bytes(n, tb, cs) <= 73728) {
-      c_fft.push_back(tb);
-      c_k2.push_back(tb);
-    }
+    if (n % tb == 0 && fft_lds_bytes(n, tb, cs) <= 73728) c_fft.push_back(tb);
+  for (int tb : {4, 8, 16}) c_k2.push_back(tb);  // the per-level slab is k2_slab(m, tb)
   for (int ch : {8, 16, 32, 64})
     if (k3_lds_bytes(p->tab, p->prec, ch)) c_k3.push_back(ch);
   if (c_fft.empty() || c_k3.empty()) return fail(BK_ERR_ARG, "no valid tile choice to tune");

@@ -108,19 +108,20 @@ __device__ __forceinline__ void stockham_pass(const cplx<T>* __restrict__ src, c
 }
 
 // The same pass with the length N and the stride NS known at compile time:
-// the index arithmetic becomes shifts and constant multiplies, and the
-// twiddle index k r (N / (NS R)) < N needs no reduction.
+// the index arithmetic becomes shifts and constant multiplies (unsigned, so
+// no sign fix-ups), and the twiddle index k r (N / (NS R)) < N needs no
+// reduction.
 template <typename T, int R, int N, int NS>
 __device__ __forceinline__ void stockham_pass_c(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst,
                                                 const cplx<T>* __restrict__ tw, int lines, int ls) {
-  constexpr int nb = N / R;
-  constexpr int tw_step = N / (NS * R);
-  const int total = lines * nb;
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int l = q / nb;
-    const int j = q - l * nb;
-    const int k = j % NS;
-    const cplx<T>* s = src + l * ls;
+  constexpr unsigned nb = N / R;
+  constexpr unsigned tw_step = N / (NS * R);
+  const unsigned total = unsigned(lines) * nb;
+  for (unsigned q = threadIdx.x; q < total; q += blockDim.x) {
+    const unsigned l = q / nb;
+    const unsigned j = q - l * nb;
+    const unsigned k = j % NS;
+    const cplx<T>* s = src + l * unsigned(ls);
     cplx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
@@ -129,7 +130,7 @@ __device__ __forceinline__ void stockham_pass_c(const cplx<T>* __restrict__ src,
       for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[k * r * tw_step]);
     }
     butterfly<T, R>(v);
-    cplx<T>* d = dst + l * ls + (j / NS) * NS * R + k;
+    cplx<T>* d = dst + l * unsigned(ls) + (j / NS) * (NS * R) + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) d[r * NS] = v[r];
   }
@@ -158,6 +159,59 @@ __device__ cplx<T>* lds_fft_c(cplx<T>* src, cplx<T>* dst, const cplx<T>* tw, int
     stockham_pass_c<T, R, N, NS>(src, dst, tw, lines, ls);
     __syncthreads();
     return lds_fft_c<T, N, S + 1, NS * R>(dst, src, tw, lines, ls);
+  }
+}
+
+// In-place variant for a block of THREADS threads transforming LINES lines of
+// a compile-time length N held in one LDS buffer (line l at buf + l * LS):
+// every thread first loads the inputs of all its butterflies, the block
+// synchronises, then every thread writes its outputs to their Stockham
+// positions.  One buffer instead of two, at the cost of one more barrier
+// per pass.
+template <typename T, int R, int N, int NS, int LINES, int THREADS, int LS>
+__device__ __forceinline__ void stockham_pass_ip(cplx<T>* __restrict__ buf, const cplx<T>* __restrict__ tw) {
+  constexpr unsigned nb = N / R;
+  constexpr unsigned total = LINES * nb;
+  constexpr unsigned bpt = (total + THREADS - 1) / THREADS;  // butterflies per thread
+  constexpr unsigned tw_step = N / (NS * R);
+  cplx<T> v[bpt][R];
+#pragma unroll
+  for (unsigned i = 0; i < bpt; ++i) {
+    const unsigned q = threadIdx.x + i * THREADS;
+    if (total % THREADS == 0 || q < total) {
+      const unsigned l = q / nb, j = q - l * nb;
+      const cplx<T>* s = buf + l * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = s[j + r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (unsigned i = 0; i < bpt; ++i) {
+    const unsigned q = threadIdx.x + i * THREADS;
+    if (total % THREADS == 0 || q < total) {
+      const unsigned l = q / nb, j = q - l * nb;
+      const unsigned k = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[k * r * tw_step]);
+      }
+      butterfly<T, R>(v[i]);
+      cplx<T>* d = buf + l * LS + (j / NS) * (NS * R) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r * NS] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// All passes of the in-place transform, starting at pass S with stride NS.
+template <typename T, int N, int LINES, int THREADS, int LS, int S = 0, int NS = 1>
+__device__ void lds_fft_ip(cplx<T>* buf, const cplx<T>* tw) {
+  if constexpr (S < Radices<N>::count) {
+    constexpr int R = Radices<N>::radix(S);
+    stockham_pass_ip<T, R, N, NS, LINES, THREADS, LS>(buf, tw);
+    lds_fft_ip<T, N, LINES, THREADS, LS, S + 1, NS * R>(buf, tw);
   }
 }
 

@@ -121,117 +121,129 @@ __global__ __launch_bounds__(256) void k_cols_kernel(cplx<T>* __restrict__ data,
 }
 
 // ---------------------------------------------------------------- K2
-// Fused ring sums on one grid level of size m (sh.n): block = (grid side gs,
-// tb consecutive columns y0..y0+tb-1).  Row transform restricted to the
-// block's columns, straight from the ring's modes (pruned DFT):
-// G(u_x, y) = sum_{u_y : (u_x,u_y) in ring} Delta(u, n) e^{-2 pi i u_y y / m},
-// then the column FFT over u_x (placed at u_x mod m) in LDS, then D at
-// gside_off[gs] + x m + y.  Delta is read from the N_g-point planes.  Every
-// ring reaching this level has 2 U < m, so no two modes share a position.
-// ring_mode_uy holds each ring's modes sorted by (u_x, u_y); ring_seg gives,
-// per ring, the start of every row u_x = -U..U (2U + 2 offsets from ring_seg_off[r]).
-template <typename T, int M>
-__global__ __launch_bounds__(256) void k2_fused_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ D,
-                                                       const int32_t* __restrict__ gside_side,
-                                                       const int64_t* __restrict__ gside_off, int gs_begin,
-                                                       long d_elems, const int32_t* __restrict__ side_ring,
-                                                       const int32_t* __restrict__ side_plane,
-                                                       const int32_t* __restrict__ side_u,
-                                                       const int32_t* __restrict__ ring_seg_off,
-                                                       const int32_t* __restrict__ ring_seg,
-                                                       const int16_t* __restrict__ ring_mode_uy, int ng, int nkeep,
-                                                       const cplx<T>* __restrict__ tw, FftShape sh, int tb) {
+// Ring sums on one grid level of size M: block = (grid side gs, TB
+// consecutive columns y0..y0+TB-1).  The row transform restricted to the
+// block's columns is a pruned DFT straight from the ring's modes,
+// G(u_x, y) = sum_{u_y : (u_x,u_y) in ring} Delta(u, n) e^{-2 pi i u_y y / M},
+// then the column FFT over u_x (placed at u_x mod M) runs in place in one LDS
+// buffer, and D is written at gside_off[gs] + x M + y.  Delta is read from the N_g-point
+// planes.  Every ring reaching this level has 2 U < M, so no two modes share
+// a position.  ring_mode_uy holds each ring's modes sorted by (u_x, u_y);
+// ring_seg gives, per ring, the start of every row u_x = -U..U (2U + 2
+// offsets from ring_seg_off[r]).
+//
+// One work item of the row transform = the two rows +u_x and -u_x (the ring is
+// symmetric, so both hold the same u_y) and kK2Cols columns.  A row's u_y are
+// symmetric, [-b, b] or [-b, -b + h - 1] and [b - h + 1, b] with h = cnt / 2
+// (checked when the plan is built), so they follow from its first mode, and
+// the four modes (+-u_x, +-v) share one twiddle w^{v y} = c - i s:
+// F(v) w^{v y} + F(-v) w^{-v y} = c S - i s A with S = F(v) + F(-v),
+// A = F(v) - F(-v).  The twiddle index advances by y per v.
+constexpr int kK2Cols = 4;      // columns per work item of the row transform
+constexpr int kK2Threads = 256;  // threads per block
+
+template <typename T, int M, int TB>
+__global__ __launch_bounds__(kK2Threads) void k2_ring_kernel(const cplx<T>* __restrict__ F, cplx<T>* __restrict__ D,
+                                                      const int32_t* __restrict__ gside_side,
+                                                      const int64_t* __restrict__ gside_off, int gs_begin,
+                                                      long d_elems, const int32_t* __restrict__ side_ring,
+                                                      const int32_t* __restrict__ side_plane,
+                                                      const int32_t* __restrict__ side_u,
+                                                      const int32_t* __restrict__ ring_seg_off,
+                                                      const int32_t* __restrict__ ring_seg,
+                                                      const int16_t* __restrict__ ring_mode_uy, int ng, int nkeep,
+                                                      const cplx<T>* __restrict__ tw) {
+  static_assert(M % TB == 0 && TB % kK2Cols == 0, "the slab must divide the grid and hold whole column groups");
+  constexpr unsigned LS = M + 1;  // padded line stride: transposed accesses hit different banks
+  constexpr unsigned CG = TB / kK2Cols;  // column groups per slab
+  constexpr unsigned YT = M / TB;        // slabs per grid side
   extern __shared__ char smem_raw[];
-  // M > 0: the grid size is the compile-time M (sh.n == M) and the FFT's
-  // index arithmetic folds to constants; M = 0: any size, from sh
-  const int m = M > 0 ? M : sh.n;
-  const int ls = m + 1;
-  const int tb_shift = __builtin_ctz(unsigned(tb));  // tb is a power of two
   cplx<T>* tw_l = reinterpret_cast<cplx<T>*>(smem_raw);
-  cplx<T>* b0 = tw_l + m;
-  cplx<T>* b1 = b0 + tb * ls;
-  for (int i = threadIdx.x; i < m; i += blockDim.x) tw_l[i] = tw[i];
-  const int ytiles = m >> tb_shift;
-  const int gs = gs_begin + int(blockIdx.x) / ytiles;
-  const int y0 = (int(blockIdx.x) - (gs - gs_begin) * ytiles) << tb_shift;
+  cplx<T>* b0 = tw_l + M;  // TB lines of LS: the row transform's output, then the column FFT in place
+  for (unsigned i = threadIdx.x; i < unsigned(M); i += blockDim.x) tw_l[i] = tw[i];
+  const unsigned gs_rel = blockIdx.x / YT;
+  const int gs = gs_begin + int(gs_rel);
+  const unsigned y0 = (blockIdx.x - gs_rel * YT) * TB;
   const int b = blockIdx.y;
   const int s = gside_side[gs];
   const int r = side_ring[s];
   const int U = side_u[s];
   const cplx<T>* Fp = F + (size_t(b) * nkeep + side_plane[s]) * size_t(ng) * ng;
   const int32_t* seg = ring_seg + ring_seg_off[r - 1];
-  for (int q = threadIdx.x; q < tb * m; q += blockDim.x) b0[(q / m) * ls + (q % m)] = {T(0), T(0)};
+  // positions no row reaches: u_x in (U, M - U)
+  for (unsigned q = threadIdx.x; q < unsigned(TB * M); q += blockDim.x) {
+    const unsigned l = q / M, i = q - l * M;
+    if (int(i) > U && int(i) < M - U) b0[l * LS + i] = {T(0), T(0)};
+  }
   __syncthreads();
-  const int nrow = 2 * U + 1;
-  const float inv_m = 1.0f / float(m);
-  // (t y) mod m without an integer division: |t| y < 2^18, exact in float32 after correction
-  auto mod_m = [&](int t) {
-    int e = t - int(float(t) * inv_m) * m;
-    e += e < 0 ? m : 0;
-    e -= e >= m ? m : 0;
-    return e;
-  };
-  // one item = one row u_x and the two columns y0 + l, y0 + l + tb / 2
-  // (one column when tb = 1)
-  const int half_shift = tb > 1 ? tb_shift - 1 : 0;
-  const int half = 1 << half_shift;
-  for (int q = threadIdx.x; q < nrow * half; q += blockDim.x) {
-    const int row = q >> half_shift, l = q & (half - 1);
-    const int ux = row - U;
-    const int nc = tb > 1 ? 2 : 1;
-    int yc[2] = {y0 + l, y0 + l + half};
-    const cplx<T>* Frow = Fp + size_t(ux < 0 ? ux + ng : ux) * ng;
-    cplx<T> acc[2] = {{T(0), T(0)}, {T(0), T(0)}};
-    const int m0 = seg[row], cnt = seg[row + 1] - m0;
+  const unsigned items = unsigned(U + 1) * CG;
+  for (unsigned q = threadIdx.x; q < items; q += blockDim.x) {
+    const int ux = int(q / CG);
+    const unsigned cg = q - unsigned(ux) * CG;
+    // columns y0 + cg + CG c, c < kK2Cols (interleaved: neighbouring threads write neighbouring lines)
+    cplx<T> ap[kK2Cols], am[kK2Cols];
+#pragma unroll
+    for (int c = 0; c < kK2Cols; ++c) ap[c] = am[c] = {T(0), T(0)};
+    const int m0 = seg[ux + U], cnt = seg[ux + U + 1] - m0;
+    const cplx<T>* rp = Fp + size_t(ux) * ng;
+    const cplx<T>* rm = Fp + size_t(ux > 0 ? ng - ux : 0) * ng;
     if (cnt > 0) {
-      // The row's u_y are symmetric: [-b, b], or [-b, -b + h - 1] and
-      // [b - h + 1, b] with h = cnt / 2 (checked when the plan is built), so
-      // they follow from the first one.  The terms of u_y = v and -v share
-      // one twiddle: F(v) w^{v y} + F(-v) w^{-v y} = c S - i s A with
-      // S = F(v) + F(-v), A = F(v) - F(-v), w^{v y} = c - i s; the twiddle
-      // index advances by y per v, and the loads of two v are issued together.
       const int bmax = -int(ring_mode_uy[m0]);
       const bool one = cnt == 2 * bmax + 1;
       const int vlo = one ? 1 : bmax - cnt / 2 + 1;
-      if (one) acc[0] = acc[1] = Frow[0];
-      const int nv = bmax - vlo + 1;
-      int e[2] = {mod_m(vlo * yc[0]), mod_m(vlo * yc[1])};
-      for (int j = 0; j < nv; j += 2) {
-        cplx<T> fp[2], fm[2];
+      if (one) {
+        const cplx<T> f0p = rp[0], f0m = rm[0];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int v = vlo + (j + i < nv ? j + i : nv - 1);
-          fp[i] = Frow[v];
-          fm[i] = Frow[ng - v];
+        for (int c = 0; c < kK2Cols; ++c) {
+          ap[c] = f0p;
+          am[c] = f0m;
         }
+      }
+      unsigned yc[kK2Cols], e[kK2Cols];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const cplx<T> sp = cadd(fp[i], fm[i]), am = csub(fp[i], fm[i]);
+      for (int c = 0; c < kK2Cols; ++c) {
+        yc[c] = y0 + cg + CG * c;
+        e[c] = (unsigned(vlo) * yc[c]) % unsigned(M);
+      }
+      // the loads of v + 1 are issued before the sums of v
+      cplx<T> fpp = rp[vlo], fpm = rp[ng - vlo], fmp = rm[vlo], fmm = rm[ng - vlo];
+      for (int v = vlo; v <= bmax; ++v) {
+        const cplx<T> sp = cadd(fpp, fpm), dp = csub(fpp, fpm);
+        const cplx<T> sm = cadd(fmp, fmm), dm = csub(fmp, fmm);
+        const int vn = v < bmax ? v + 1 : v;
+        fpp = rp[vn];
+        fpm = rp[ng - vn];
+        fmp = rm[vn];
+        fmm = rm[ng - vn];
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            if (j + i < nv) {
-              const cplx<T> w = tw_l[e[c]];  // (c, -s)
-              acc[c] = cadd(acc[c], cplx<T>{w.x * sp.x - w.y * am.y, w.x * sp.y + w.y * am.x});
-            }
-            e[c] += yc[c];
-            e[c] -= e[c] >= m ? m : 0;
-          }
+        for (int c = 0; c < kK2Cols; ++c) {
+          const cplx<T> w = tw_l[e[c]];  // (c, -s)
+          ap[c].x = fma(w.x, sp.x, ap[c].x);
+          ap[c].x = fma(-w.y, dp.y, ap[c].x);
+          ap[c].y = fma(w.x, sp.y, ap[c].y);
+          ap[c].y = fma(w.y, dp.x, ap[c].y);
+          am[c].x = fma(w.x, sm.x, am[c].x);
+          am[c].x = fma(-w.y, dm.y, am[c].x);
+          am[c].y = fma(w.x, sm.y, am[c].y);
+          am[c].y = fma(w.y, dm.x, am[c].y);
+          e[c] += yc[c];
+          e[c] -= e[c] >= unsigned(M) ? unsigned(M) : 0u;
         }
       }
     }
-    const int pos = ux < 0 ? ux + m : ux;
-    for (int c = 0; c < nc; ++c) b0[(l + c * half) * ls + pos] = acc[c];
+#pragma unroll
+    for (int c = 0; c < kK2Cols; ++c) {
+      cplx<T>* line = b0 + (cg + CG * c) * LS;
+      line[ux] = ap[c];
+      if (ux > 0) line[M - ux] = am[c];
+    }
   }
   __syncthreads();
-  cplx<T>* res;
-  if constexpr (M > 0)
-    res = lds_fft_c<T, M>(b0, b1, tw_l, tb, ls);
-  else
-    res = lds_fft(b0, b1, tw_l, sh, tb, ls);
-  cplx<T>* Ds = D + size_t(b) * d_elems + gside_off[gs];
-  for (int q = threadIdx.x; q < tb * m; q += blockDim.x) {
-    const int x = q >> tb_shift, l = q & (tb - 1);
-    Ds[size_t(x) * m + y0 + l] = res[l * ls + x];
+  lds_fft_ip<T, M, TB, kK2Threads, LS>(b0, tw_l);
+  cplx<T>* Ds = D + size_t(b) * d_elems + gside_off[gs] + y0;
+  for (unsigned q = threadIdx.x; q < unsigned(TB * M); q += blockDim.x) {
+    const unsigned x = q / TB, l = q - x * TB;
+    Ds[size_t(x) * M + l] = b0[l * LS + x];
   }
 }
 
