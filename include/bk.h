@@ -105,6 +105,21 @@ typedef struct {
  * BK_K3_SIDES (staged sides per workgroup, 1..254).  An invalid combination
  * fails with BK_ERR_ARG. */
 bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int max_batch, bk_plan* out);
+
+/* A plan with several second-level binnings ("resolutions") of the same
+ * combinations, as the validation of Sec. III uses finer (mu, t) bins for
+ * low l than for high l.  Resolution 0 is `binning`'s own (n_k1, n_mu, n_t);
+ * resolution r = 1..n_extra has the counts extra_bins[3(r-1) .. 3(r-1)+2]
+ * (n_k1, n_mu, n_t), on the same k1 range and (l, m) list.  One estimate
+ * runs the FFTs, ring sums and triple products once and the binning of
+ * Eq. 13 once per resolution; every resolution's outputs are bit-identical
+ * to those of a separate plan created with that binning.  Read them with the
+ * *_res calls below (the calls without _res read resolution 0).  Errors as
+ * bk_plan_create, plus BK_ERR_ARG if n_extra is not in [0, 7], extra_bins is
+ * NULL with n_extra > 0, a count is < 1 or a resolution has over 10^7 bins.
+ * bk_plan_create(b, ...) is bk_plan_create_multires(b, NULL, 0, ...). */
+bk_status bk_plan_create_multires(const bk_binning* binning, const int* extra_bins, int n_extra, int prec, int device,
+                                  int max_batch, bk_plan* out);
 bk_status bk_plan_destroy(bk_plan plan);
 
 /* Copy `batch` fields delta(x), C order [batch][x][y][z] (z = line of sight),
@@ -156,6 +171,19 @@ bk_status bk_get_triangle_counts(bk_plan plan, int64_t* out, size_t cap);
 /* N_tri-weighted mean (k1, mu, t) of each bin (Eq. 2 on the combinations'
  * mean-value sides, weighted as in Eq. 13), float64 [n_bins][3]; NaN if empty. */
 bk_status bk_get_bin_means(bk_plan plan, double* k1_mu_t, size_t cap);
+
+/* Number of resolutions of the plan (1 + n_extra; 0 for a NULL plan). */
+int bk_n_resolutions(bk_plan plan);
+
+/* Bins per axis of resolution `res`.  BK_ERR_ARG if res is out of range. */
+bk_status bk_query_resolution(bk_plan plan, int res, int* n_k1, int* n_mu, int* n_t);
+
+/* bk_get_multipoles, bk_get_triangle_counts and bk_get_bin_means for
+ * resolution `res` (its n_k1 x n_mu x n_t bins).  BK_ERR_ARG if res is out of
+ * range; otherwise the same layout, synchronisation and errors. */
+bk_status bk_get_multipoles_res(bk_plan plan, int res, double* out, size_t cap);
+bk_status bk_get_triangle_counts_res(bk_plan plan, int res, int64_t* out, size_t cap);
+bk_status bk_get_bin_means_res(bk_plan plan, int res, double* k1_mu_t, size_t cap);
 
 /* Plan statistics, float64 [cap] with 9 <= cap (11 filled at most):
  * combinations (an n -> -n partner pair counted once), work items, sides,
@@ -283,7 +311,8 @@ bk_status bk_debug_mfma_probe(int prec, double* out, size_t cap);
  * Delta planes, ring sums, contraction outputs and binning partials live in a
  * static device array of the library, 64 MiB per device (enough for one
  * N_g = 64 field in float64, two in float32), held by each device the library
- * runs on until the process ends.  The call allocates nothing, enqueues the
+ * runs on until the process ends.  Only resolution 0 is binned (a plan's
+ * extra resolutions are left to bk_estimate).  The call allocates nothing, enqueues the
  * kernels on hip_stream and returns; it does not touch the plan's loaded
  * fields, results or stage times.  Errors: BK_ERR_ARG for null pointers, a
  * bad dtype or batch < 1; BK_ERR_SIZE (nothing launched) if the plan's

@@ -64,7 +64,14 @@ _lib = None
 _SIGS = {
     "bk_plan_create": [ctypes.POINTER(bk_binning), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                        ctypes.POINTER(ctypes.c_void_p)],
+    "bk_plan_create_multires": [ctypes.POINTER(bk_binning), ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
     "bk_plan_destroy": [ctypes.c_void_p],
+    "bk_n_resolutions": [ctypes.c_void_p],
+    "bk_query_resolution": [ctypes.c_void_p, ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3,
+    "bk_get_multipoles_res": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+    "bk_get_triangle_counts_res": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_size_t],
+    "bk_get_bin_means_res": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
     "bk_load_grid": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "bk_estimate": [ctypes.c_void_p, ctypes.c_void_p],
     "bk_estimate_timed": [ctypes.c_void_p, ctypes.c_void_p],
@@ -131,6 +138,52 @@ def bk_plan_create(binning: bk_binning, prec: int = BK_F32, device: int = 0, max
     out = ctypes.c_void_p()
     _check(lib().bk_plan_create(ctypes.byref(binning), int(prec), int(device), int(max_batch), ctypes.byref(out)))
     return out.value
+
+
+def bk_plan_create_multires(binning: bk_binning, extra_bins, prec: int = BK_F32, device: int = 0,
+                            max_batch: int = 1) -> int:
+    """extra_bins: sequence of (n_k1, n_mu, n_t) for resolutions 1, 2, ..."""
+    flat = [int(x) for d in extra_bins for x in d]
+    arr = (ctypes.c_int * max(1, len(flat)))(*flat)
+    out = ctypes.c_void_p()
+    _check(lib().bk_plan_create_multires(ctypes.byref(binning), arr, len(flat) // 3, int(prec), int(device),
+                                         int(max_batch), ctypes.byref(out)))
+    return out.value
+
+
+def bk_n_resolutions(plan: int) -> int:
+    return int(lib().bk_n_resolutions(ctypes.c_void_p(plan)))
+
+
+def bk_query_resolution(plan: int, res: int):
+    v = [ctypes.c_int() for _ in range(3)]
+    _check(lib().bk_query_resolution(ctypes.c_void_p(plan), int(res), *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def bk_get_multipoles_res(plan: int, res: int, batch: int) -> np.ndarray:
+    n_lm = bk_query_sizes(plan)[0]
+    n_k1, n_mu, n_t = bk_query_resolution(plan, res)
+    out = np.empty(batch * n_lm * n_k1 * n_mu * n_t, dtype=np.float64)
+    _check(lib().bk_get_multipoles_res(ctypes.c_void_p(plan), int(res),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return out.reshape(batch, n_lm, n_k1, n_mu, n_t)
+
+
+def bk_get_triangle_counts_res(plan: int, res: int) -> np.ndarray:
+    n_k1, n_mu, n_t = bk_query_resolution(plan, res)
+    out = np.empty(n_k1 * n_mu * n_t, dtype=np.int64)
+    _check(lib().bk_get_triangle_counts_res(ctypes.c_void_p(plan), int(res),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.size))
+    return out.reshape(n_k1, n_mu, n_t)
+
+
+def bk_get_bin_means_res(plan: int, res: int) -> np.ndarray:
+    n_k1, n_mu, n_t = bk_query_resolution(plan, res)
+    out = np.empty(n_k1 * n_mu * n_t * 3, dtype=np.float64)
+    _check(lib().bk_get_bin_means_res(ctypes.c_void_p(plan), int(res),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+    return out.reshape(n_k1, n_mu, n_t, 3)
 
 
 def bk_plan_destroy(plan: int):
@@ -318,10 +371,14 @@ def bk_group_destroy(group: int):
 class Estimator:
     """A plan plus convenience methods taking torch tensors or numpy arrays."""
 
-    def __init__(self, binning: bk_binning, prec: int = BK_F32, device: int = 0, max_batch: int = 1):
+    def __init__(self, binning: bk_binning, prec: int = BK_F32, device: int = 0, max_batch: int = 1,
+                 extra_bins=()):
         self.binning = binning
         self.prec = prec
-        self.plan = bk_plan_create(binning, prec, device, max_batch)
+        if extra_bins:
+            self.plan = bk_plan_create_multires(binning, extra_bins, prec, device, max_batch)
+        else:
+            self.plan = bk_plan_create(binning, prec, device, max_batch)
         self.batch = 0
 
     def close(self):
@@ -362,11 +419,14 @@ class Estimator:
     def estimate_timed(self, stream: int = 0):
         bk_estimate_timed(self.plan, stream)
 
-    def multipoles(self) -> np.ndarray:
-        return bk_get_multipoles(self.plan, self.batch)
+    def multipoles(self, res: int = 0) -> np.ndarray:
+        return bk_get_multipoles_res(self.plan, res, self.batch)
 
-    def counts(self) -> np.ndarray:
-        return bk_get_triangle_counts(self.plan)
+    def counts(self, res: int = 0) -> np.ndarray:
+        return bk_get_triangle_counts_res(self.plan, res)
+
+    def bin_means(self, res: int = 0) -> np.ndarray:
+        return bk_get_bin_means_res(self.plan, res)
 
     def lm_list(self):
         return bk_get_lm_list(self.plan)

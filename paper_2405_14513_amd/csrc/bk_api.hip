@@ -56,6 +56,19 @@ bool fft_shape(int n, bk::FftShape* sh) {
 
 }  // namespace
 
+// Device tables and outputs of the binning (K4) at one resolution.
+struct K4Res {
+  int n_bins = 0;
+  long n_chunks = 0;
+  long* d_chunk_begin = nullptr;  // combination index where each chunk starts [n_chunks + 1]
+  long* d_bin_chunk = nullptr;    // first chunk of each bin [n_bins + 1]
+  int32_t* d_combo_slot = nullptr;
+  void* d_coef = nullptr;         // per-combination coefficients, float32 (BK_F32 plans) or float64
+  unsigned char* d_empty = nullptr;
+  double* d_part = nullptr;       // partial sums [max_batch][n_chunks][n_lm]
+  double* d_B = nullptr;          // [max_batch][n_lm][n_bins]
+};
+
 struct bk_plan_s {
   bk::Tables tab;
   int prec = BK_F64;
@@ -84,7 +97,6 @@ struct bk_plan_s {
   void* d_F = nullptr;        // [max_batch][nkeep][N][N] complex
   void* d_D = nullptr;        // [max_batch][d_elems] complex: every grid side's m x m points
   double* d_S = nullptr;      // [max_batch][n_items][512]
-  double* d_B = nullptr;      // [max_batch][n_lm][n_bins]
   void* d_tw = nullptr;       // twiddles, N complex
   void* d_tw_lv = nullptr;    // twiddles of every grid level, m complex each, at tw_lv_off
   std::vector<long> tw_lv_off;
@@ -97,17 +109,11 @@ struct bk_plan_s {
   int32_t* d_side_ring = nullptr;
   int32_t* d_side_plane = nullptr;
   int32_t* d_side_u = nullptr;
-  long* d_bin_ptr = nullptr;
   int32_t* d_ring_seg_off = nullptr;  // per ring: offset of its row table in d_ring_seg
   int32_t* d_ring_seg = nullptr;      // per ring: start of each row u_x = -U..U in the mode list, plus end
   int16_t* d_ring_mode_uy = nullptr;  // every ring's modes sorted by (u_x, u_y): u_y
-  long* d_chunk_begin = nullptr;  // combination index where each K4 chunk starts [n_chunks + 1]
-  long* d_bin_chunk = nullptr;    // first chunk of each bin [n_bins + 1]
-  double* d_part = nullptr;       // K4 partial sums [max_batch][n_chunks][n_lm]
-  long n_chunks = 0;
-  int32_t* d_combo_slot = nullptr;
-  void* d_coef = nullptr;         // per-combination coefficients, float32 (BK_F32 plans) or float64
-  unsigned char* d_empty = nullptr;
+  // the binning of every resolution (res[0]: the plan's binning)
+  std::vector<K4Res> k4;
   // Stage events: launch_all records the five stage boundaries into `ev`,
   // which points at one of kEvSets sets used in turn by consecutive timed
   // estimates; ev_count sets (the latest ones) belong to timed estimates of
@@ -166,13 +172,17 @@ bk_status put(bk_plan p, V** dptr, const V* host, size_t count) {
 
 void release(bk_plan p) {
   void* ptrs[] = {p->d_in,         p->d_F,          p->d_D,          p->d_S,
-                  p->d_B,          p->d_tw,         p->d_groups,     p->d_items,      p->d_group_sides,
+                  p->d_tw,         p->d_groups,     p->d_items,      p->d_group_sides,
                   p->d_side_ring,  p->d_side_plane, p->d_side_u,
-                  p->d_bin_ptr,    p->d_combo_slot, p->d_coef,       p->d_empty,
-                  p->d_chunk_begin, p->d_bin_chunk, p->d_part,     p->d_ring_seg_off, p->d_ring_seg,
+                  p->d_ring_seg_off, p->d_ring_seg,
                   p->d_ring_mode_uy, p->d_tw_lv,   p->d_gs_side,  p->d_gs_off};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (K4Res& k : p->k4) {
+    void* kp[] = {k.d_chunk_begin, k.d_bin_chunk, k.d_combo_slot, k.d_coef, k.d_empty, k.d_part, k.d_B};
+    for (void* q : kp)
+      if (q) (void)hipFree(q);
+  }
   if (p->have_events)
     for (auto& set : p->evs)
       for (auto& e : set)
@@ -192,8 +202,9 @@ struct Bufs {
   void* F = nullptr;         // [batch][nkeep][N][N] complex
   void* D = nullptr;         // [batch][d_elems] complex
   double* S = nullptr;       // [batch][n_items][item_out]
-  double* part = nullptr;    // [batch][n_chunks][n_lm]
-  double* B = nullptr;       // [batch][n_lm][n_bins]
+  double* part = nullptr;    // [batch][n_chunks][n_lm] of the first resolution
+  double* B = nullptr;       // [batch][n_lm][n_bins] of the first resolution
+  bool first_res_only = false;  // bin at the first resolution only (else every resolution, into the plan's buffers)
   bool skip_fft = false;     // D is already set: run the contraction and the binning only
 };
 
@@ -205,8 +216,8 @@ Bufs plan_bufs(bk_plan p) {
   b.F = p->d_F;
   b.D = p->d_D;
   b.S = p->d_S;
-  b.part = p->d_part;
-  b.B = p->d_B;
+  b.part = p->k4[0].d_part;
+  b.B = p->k4[0].d_B;
   b.skip_fft = p->d_injected != 0;
   return b;
 }
@@ -444,31 +455,34 @@ bk_status launch_all(bk_plan p, const Bufs& bf, hipStream_t st, bool timing) {
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[3], st));
-  // K4: binning
-  {
-    const int n_bins = p->tab.bin.n_k1 * p->tab.bin.n_mu * p->tab.bin.n_t;
-    dim3 g4(n_bins, B);
-    const int nlm = int(p->tab.lm_l.size());
-    const long s_per = p->n_items * long(p->item_out);
-    unsigned long long odd_mask = 0;
-    for (int j = 0; j < nlm; ++j)
-      if (p->tab.lm_l[j] % 2) odd_mask |= 1ull << j;
-    const long im_off = long(p->tab.k3.pairs_per_item) * bk::kTileN;  // Im S follows Re S in every item
-    if (p->n_chunks > 0) {
-      dim3 gp(p->n_chunks, B);
+  // K4: binning, at every resolution
+  const int nlm = int(p->tab.lm_l.size());
+  unsigned long long odd_mask = 0;
+  for (int j = 0; j < nlm; ++j)
+    if (p->tab.lm_l[j] % 2) odd_mask |= 1ull << j;
+  const long s_per = p->n_items * long(p->item_out);
+  const long im_off = long(p->tab.k3.pairs_per_item) * bk::kTileN;  // Im S follows Re S in every item
+  const size_t n_res = bf.first_res_only ? 1 : p->k4.size();
+  for (size_t r = 0; r < n_res; ++r) {
+    const K4Res& k = p->k4[r];
+    double* part = r == 0 ? bf.part : k.d_part;
+    double* Bout = r == 0 ? bf.B : k.d_B;
+    const T* coef = reinterpret_cast<const T*>(k.d_coef);
+    if (k.n_chunks > 0) {
+      dim3 gp(k.n_chunks, B);
       if (nlm <= 16)
-        hipLaunchKernelGGL((bk::k4_partial_kernel<16, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<16, T>), gp, dim3(64), 0, st, bf.S, s_per, k.d_chunk_begin,
+                           k.d_combo_slot, coef, nlm, k.n_chunks, odd_mask, im_off, part);
       else if (nlm <= 32)
-        hipLaunchKernelGGL((bk::k4_partial_kernel<32, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<32, T>), gp, dim3(64), 0, st, bf.S, s_per, k.d_chunk_begin,
+                           k.d_combo_slot, coef, nlm, k.n_chunks, odd_mask, im_off, part);
       else
-        hipLaunchKernelGGL((bk::k4_partial_kernel<64, T>), gp, dim3(64), 0, st, bf.S, s_per, p->d_chunk_begin,
-                           p->d_combo_slot, reinterpret_cast<const T*>(p->d_coef), nlm, p->n_chunks, odd_mask, im_off, bf.part);
+        hipLaunchKernelGGL((bk::k4_partial_kernel<64, T>), gp, dim3(64), 0, st, bf.S, s_per, k.d_chunk_begin,
+                           k.d_combo_slot, coef, nlm, k.n_chunks, odd_mask, im_off, part);
       BK_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(bk::k4_finish_kernel, g4, dim3(64), 0, st, bf.part, p->n_chunks, p->d_bin_chunk, p->d_empty,
-                       nlm, n_bins, p->norm, bf.B);
+    hipLaunchKernelGGL(bk::k4_finish_kernel, dim3(k.n_bins, B), dim3(64), 0, st, part, k.n_chunks, k.d_bin_chunk,
+                       k.d_empty, nlm, k.n_bins, p->norm, Bout);
     BK_HIP(hipGetLastError());
   }
   if (timing) BK_HIP(hipEventRecord(p->ev[4], st));
@@ -591,7 +605,7 @@ extern "C" bk_status bk_count_triangles(const bk_binning* bn, int64_t* out, size
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
   }
   if (!err.empty()) return fail(BK_ERR_ARG, err);
-  std::copy(T.bin_count.begin(), T.bin_count.end(), out);
+  std::copy(T.res[0].bin_count.begin(), T.res[0].bin_count.end(), out);
   if (n_comb) *n_comb = T.n_combos;
   return BK_OK;
 }
@@ -620,8 +634,9 @@ extern "C" bk_status bk_discrete_prediction(const bk_binning* bn, const bk_model
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
   }
   if (!err.empty()) return fail(BK_ERR_ARG, err);
-  if (T.model_pred.size() != n_out) return fail(BK_ERR_ARG, "internal: prediction size mismatch");
-  std::copy(T.model_pred.begin(), T.model_pred.end(), out);
+  const std::vector<double>& pred = T.res[0].model_pred;
+  if (pred.size() != n_out) return fail(BK_ERR_ARG, "internal: prediction size mismatch");
+  std::copy(pred.begin(), pred.end(), out);
   return BK_OK;
 }
 
@@ -640,16 +655,31 @@ extern "C" bk_status bk_continuum_multipoles(int l_max, int m_max, double mu, do
 }
 
 extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, int max_batch, bk_plan* out) {
+  return bk_plan_create_multires(bn, nullptr, 0, prec, device, max_batch, out);
+}
+
+extern "C" bk_status bk_plan_create_multires(const bk_binning* bn, const int* extra_bins, int n_extra, int prec,
+                                             int device, int max_batch, bk_plan* out) {
   g_last_error.clear();
   if (!bn || !out) return fail(BK_ERR_ARG, "null argument");
   *out = nullptr;
   if (prec != BK_F32 && prec != BK_F64) return fail(BK_ERR_ARG, "prec must be BK_F32 or BK_F64");
   if (max_batch < 1) return fail(BK_ERR_ARG, "max_batch must be >= 1");
+  if (n_extra < 0 || n_extra > bk::kMaxResolutions - 1 || (n_extra > 0 && !extra_bins))
+    return fail(BK_ERR_ARG, "n_extra must be in [0, " + std::to_string(bk::kMaxResolutions - 1) +
+                                "] with extra_bins holding 3 * n_extra counts");
   bk::FftShape sh{};
   bk::Binning b;
   {
     bk_status cst = check_binning(bn, &sh, &b);
     if (cst != BK_OK) return cst;
+  }
+  std::vector<std::array<int, 3>> extra;
+  for (int r = 0; r < n_extra; ++r) {
+    const std::array<int, 3> d{extra_bins[3 * r], extra_bins[3 * r + 1], extra_bins[3 * r + 2]};
+    if (d[0] < 1 || d[1] < 1 || d[2] < 1) return fail(BK_ERR_ARG, "bin counts must be >= 1");
+    if (double(d[0]) * d[1] * d[2] > 1e7) return fail(BK_ERR_ARG, "at most 10^7 bins per resolution");
+    extra.push_back(d);
   }
   int ndev = 0;
   BK_HIP(hipGetDeviceCount(&ndev));
@@ -684,7 +714,7 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
   try {
-    err = bk::build_tables(b, shape, host_threads(), &p->tab);
+    err = bk::build_tables(b, shape, host_threads(), &p->tab, nullptr, false, extra);
   } catch (const std::bad_alloc&) {
     delete p;
     return fail(BK_ERR_OOM, "host allocation failed while building tables");
@@ -758,7 +788,6 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   std::vector<float> twf(twd.begin(), twd.end());
 
   bk_status st = BK_OK;
-  const int n_bins = b.n_k1 * b.n_mu * b.n_t;
   const int nlm = int(T.lm_l.size());
 #define TRY(x)              \
   do {                      \
@@ -798,7 +827,6 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(put(p, &p->d_gs_side, T.gside_side.data(), T.gside_side.size()));
   TRY(put(p, &p->d_gs_off, T.gside_off.data(), T.gside_off.size()));
   TRY(dalloc(p, reinterpret_cast<void**>(&p->d_S), size_t(max_batch) * size_t(p->n_items) * p->item_out * 8));
-  TRY(dalloc(p, reinterpret_cast<void**>(&p->d_B), size_t(max_batch) * nlm * n_bins * 8));
   if (prec == BK_F32)
     TRY(put(p, reinterpret_cast<float**>(&p->d_tw), twf.data(), twf.size()));
   else
@@ -809,43 +837,48 @@ extern "C" bk_status bk_plan_create(const bk_binning* bn, int prec, int device, 
   TRY(put(p, &p->d_side_ring, T.side_ring.data(), T.side_ring.size()));
   TRY(put(p, &p->d_side_plane, T.side_plane.data(), T.side_plane.size()));
   TRY(put(p, &p->d_side_u, side_u.data(), side_u.size()));
-  std::vector<long> bin_ptr(T.bin_ptr.begin(), T.bin_ptr.end());
   if (long(p->n_items) * p->item_out * max_batch >= (1L << 31)) {
     release(p);
     delete p;
     return fail(BK_ERR_ARG, "too many work items for 32-bit output slots");
   }
-  std::vector<int32_t> cslot(T.combo_slot.begin(), T.combo_slot.end());
-  {
-    std::vector<long> chunk_begin, bin_chunk(n_bins + 1, 0);
-    for (int bin = 0; bin < n_bins; ++bin) {
+  p->k4.resize(T.res.size());
+  for (size_t r = 0; r < T.res.size(); ++r) {
+    bk::Resolution& R = T.res[r];
+    K4Res& k = p->k4[r];
+    k.n_bins = R.n_bins();
+    std::vector<long> chunk_begin, bin_chunk(k.n_bins + 1, 0);
+    for (int bin = 0; bin < k.n_bins; ++bin) {
       bin_chunk[bin] = long(chunk_begin.size());
-      for (long c = bin_ptr[bin]; c < bin_ptr[bin + 1]; c += bk::kK4Chunk) chunk_begin.push_back(c);
+      for (long c = R.bin_ptr[bin]; c < R.bin_ptr[bin + 1]; c += bk::kK4Chunk) chunk_begin.push_back(c);
     }
-    bin_chunk[n_bins] = long(chunk_begin.size());
-    p->n_chunks = long(chunk_begin.size());
-    chunk_begin.push_back(bin_ptr[n_bins]);
+    bin_chunk[k.n_bins] = long(chunk_begin.size());
+    k.n_chunks = long(chunk_begin.size());
+    chunk_begin.push_back(R.bin_ptr[k.n_bins]);
     // chunks are consecutive and start at every bin start, so none crosses a bin
-    TRY(put(p, &p->d_chunk_begin, chunk_begin.data(), chunk_begin.size()));
-    TRY(put(p, &p->d_bin_chunk, bin_chunk.data(), bin_chunk.size()));
-    TRY(dalloc(p, reinterpret_cast<void**>(&p->d_part), size_t(max_batch) * std::max(1L, p->n_chunks) * nlm * 8));
+    TRY(put(p, &k.d_chunk_begin, chunk_begin.data(), chunk_begin.size()));
+    TRY(put(p, &k.d_bin_chunk, bin_chunk.data(), bin_chunk.size()));
+    TRY(dalloc(p, reinterpret_cast<void**>(&k.d_part), size_t(max_batch) * std::max(1L, k.n_chunks) * nlm * 8));
+    TRY(dalloc(p, reinterpret_cast<void**>(&k.d_B), size_t(max_batch) * nlm * k.n_bins * 8));
+    {
+      std::vector<int32_t> cslot(R.combo_slot.begin(), R.combo_slot.end());
+      TRY(put(p, &k.d_combo_slot, cslot.data(), cslot.size()));
+    }
+    // Coefficients in the plan's precision: float32 rounding (2^-24 relative)
+    // of each coefficient is far below the float32 path's error, and halves
+    // the bytes the binning reads; the per-bin sums stay float64.
+    if (prec == BK_F32) {
+      std::vector<float> c32(R.combo_coef.begin(), R.combo_coef.end());
+      TRY(put(p, reinterpret_cast<float**>(&k.d_coef), c32.data(), c32.size()));
+    } else {
+      TRY(put(p, reinterpret_cast<double**>(&k.d_coef), R.combo_coef.data(), R.combo_coef.size()));
+    }
+    TRY(put(p, &k.d_empty, R.bin_empty_lm.data(), R.bin_empty_lm.size()));
+    // the host copies of the per-combination arrays are no longer needed
+    std::vector<double>().swap(R.combo_coef);
+    std::vector<int64_t>().swap(R.combo_slot);
   }
-  TRY(put(p, &p->d_bin_ptr, bin_ptr.data(), bin_ptr.size()));
-  TRY(put(p, &p->d_combo_slot, cslot.data(), cslot.size()));
-  // Coefficients in the plan's precision: float32 rounding (2^-24 relative)
-  // of each coefficient is far below the float32 path's error, and halves
-  // the bytes the binning reads; the per-bin sums stay float64.
-  if (prec == BK_F32) {
-    std::vector<float> c32(T.combo_coef.begin(), T.combo_coef.end());
-    TRY(put(p, reinterpret_cast<float**>(&p->d_coef), c32.data(), c32.size()));
-  } else {
-    TRY(put(p, reinterpret_cast<double**>(&p->d_coef), T.combo_coef.data(), T.combo_coef.size()));
-  }
-  TRY(put(p, &p->d_empty, T.bin_empty_lm.data(), T.bin_empty_lm.size()));
 #undef TRY
-  // the host copies of the per-combination arrays are no longer needed
-  std::vector<double>().swap(T.combo_coef);
-  std::vector<int64_t>().swap(T.combo_slot);
 
   {
     // largest chunk whose two staging buffers fit 80 KiB (at least two
@@ -973,9 +1006,9 @@ bk_status bk_query_sizes(bk_plan p, int* n_lm, int* n_k1, int* n_mu, int* n_t) {
   g_last_error.clear();
   if (!p) return fail(BK_ERR_ARG, "null plan");
   if (n_lm) *n_lm = int(p->tab.lm_l.size());
-  if (n_k1) *n_k1 = p->tab.bin.n_k1;
-  if (n_mu) *n_mu = p->tab.bin.n_mu;
-  if (n_t) *n_t = p->tab.bin.n_t;
+  if (n_k1) *n_k1 = p->tab.res[0].n_k1;
+  if (n_mu) *n_mu = p->tab.res[0].n_mu;
+  if (n_t) *n_t = p->tab.res[0].n_t;
   return BK_OK;
 }
 
@@ -991,34 +1024,59 @@ bk_status bk_get_lm_list(bk_plan p, int* lm, size_t cap) {
   return BK_OK;
 }
 
-bk_status bk_get_multipoles(bk_plan p, double* out, size_t cap) {
+bk_status bk_query_resolution(bk_plan p, int res, int* n_k1, int* n_mu, int* n_t) {
+  g_last_error.clear();
+  if (!p) return fail(BK_ERR_ARG, "null plan");
+  if (res < 0 || res >= int(p->tab.res.size())) return fail(BK_ERR_ARG, "no such resolution");
+  const bk::Resolution& R = p->tab.res[res];
+  if (n_k1) *n_k1 = R.n_k1;
+  if (n_mu) *n_mu = R.n_mu;
+  if (n_t) *n_t = R.n_t;
+  return BK_OK;
+}
+
+int bk_n_resolutions(bk_plan p) { return p ? int(p->tab.res.size()) : 0; }
+
+bk_status bk_get_multipoles_res(bk_plan p, int res, double* out, size_t cap) {
   g_last_error.clear();
   if (!p || !out) return fail(BK_ERR_ARG, "null argument");
+  if (res < 0 || res >= int(p->k4.size())) return fail(BK_ERR_ARG, "no such resolution");
   if (!p->estimated) return fail(BK_ERR_STATE, "no estimate has been run for the loaded grid");
-  const size_t n_bins = size_t(p->tab.bin.n_k1) * p->tab.bin.n_mu * p->tab.bin.n_t;
-  const size_t need = size_t(p->batch) * p->tab.lm_l.size() * n_bins;
+  const size_t need = size_t(p->batch) * p->tab.lm_l.size() * size_t(p->k4[res].n_bins);
   if (cap < need) return fail(BK_ERR_SIZE, "output buffer too small");
   BK_HIP(hipSetDevice(p->device));
   BK_HIP(hipStreamSynchronize(p->stream));
-  BK_HIP(hipMemcpy(out, p->d_B, need * sizeof(double), hipMemcpyDeviceToHost));
+  BK_HIP(hipMemcpy(out, p->k4[res].d_B, need * sizeof(double), hipMemcpyDeviceToHost));
+  return BK_OK;
+}
+
+bk_status bk_get_multipoles(bk_plan p, double* out, size_t cap) { return bk_get_multipoles_res(p, 0, out, cap); }
+
+bk_status bk_get_triangle_counts_res(bk_plan p, int res, int64_t* out, size_t cap) {
+  g_last_error.clear();
+  if (!p || !out) return fail(BK_ERR_ARG, "null argument");
+  if (res < 0 || res >= int(p->tab.res.size())) return fail(BK_ERR_ARG, "no such resolution");
+  const bk::Resolution& R = p->tab.res[res];
+  if (cap < R.bin_count.size()) return fail(BK_ERR_SIZE, "output buffer too small");
+  std::copy(R.bin_count.begin(), R.bin_count.end(), out);
   return BK_OK;
 }
 
 bk_status bk_get_triangle_counts(bk_plan p, int64_t* out, size_t cap) {
+  return bk_get_triangle_counts_res(p, 0, out, cap);
+}
+
+bk_status bk_get_bin_means_res(bk_plan p, int res, double* out, size_t cap) {
   g_last_error.clear();
   if (!p || !out) return fail(BK_ERR_ARG, "null argument");
-  if (cap < p->tab.bin_count.size()) return fail(BK_ERR_SIZE, "output buffer too small");
-  std::copy(p->tab.bin_count.begin(), p->tab.bin_count.end(), out);
+  if (res < 0 || res >= int(p->tab.res.size())) return fail(BK_ERR_ARG, "no such resolution");
+  const bk::Resolution& R = p->tab.res[res];
+  if (cap < R.bin_mean.size()) return fail(BK_ERR_SIZE, "output buffer too small");
+  std::copy(R.bin_mean.begin(), R.bin_mean.end(), out);
   return BK_OK;
 }
 
-bk_status bk_get_bin_means(bk_plan p, double* out, size_t cap) {
-  g_last_error.clear();
-  if (!p || !out) return fail(BK_ERR_ARG, "null argument");
-  if (cap < p->tab.bin_mean.size()) return fail(BK_ERR_SIZE, "output buffer too small");
-  std::copy(p->tab.bin_mean.begin(), p->tab.bin_mean.end(), out);
-  return BK_OK;
-}
+bk_status bk_get_bin_means(bk_plan p, double* out, size_t cap) { return bk_get_bin_means_res(p, 0, out, cap); }
 
 bk_status bk_get_plan_info(bk_plan p, double* info, size_t cap) {
   g_last_error.clear();
@@ -1422,7 +1480,7 @@ extern "C" bk_status bk_estimate_noalloc(bk_plan p, const void* delta, int dtype
   const size_t f_bytes = align256(b * p->nkeep * n2 * cs);
   const size_t d_bytes = align256(b * size_t(p->tab.d_elems) * cs);
   const size_t s_bytes = align256(b * size_t(p->n_items) * size_t(p->item_out) * sizeof(double));
-  const size_t part_bytes = align256(b * size_t(std::max(1L, p->n_chunks)) * nlm * sizeof(double));
+  const size_t part_bytes = align256(b * size_t(std::max(1L, p->k4[0].n_chunks)) * nlm * sizeof(double));
   const size_t need = f_bytes + d_bytes + s_bytes + part_bytes;
   if (need > kScratchBytes)
     return fail(BK_ERR_SIZE, "this plan needs " + std::to_string(need) + " bytes of scratch for " +
@@ -1442,6 +1500,7 @@ extern "C" bk_status bk_estimate_noalloc(bk_plan p, const void* delta, int dtype
   bf.S = reinterpret_cast<double*>(c + f_bytes + d_bytes);
   bf.part = reinterpret_cast<double*>(c + f_bytes + d_bytes + s_bytes);
   bf.B = B_out;
+  bf.first_res_only = true;
   // every scratch element an estimate reads was written earlier in the same
   // estimate, so nothing needs clearing between calls
   hipStream_t hs = reinterpret_cast<hipStream_t>(hip_stream);

@@ -51,6 +51,18 @@ struct Candidate {
   int32_t ra, rb, rc;  // rings of slots A (plane a), B (plane b), C (plane -(a+b))
 };
 
+// Bin of a kept shape (k1, mu, t) among dims = (n_k1, n_mu, n_t) equal bins
+// of [k1_min, k1_max) x [1/2, 1] x [1/2, 1]; the upper edges fall in the last bin.
+int bin_index(double k1_min, double k1_max, const std::array<int, 3>& dims, double k1, double mu, double tt) {
+  const double dk = (k1_max - k1_min) / double(dims[0]);
+  const double dmu = 0.5 / double(dims[1]);
+  const double dt = 0.5 / double(dims[2]);
+  const int ik = std::min(int(std::floor((k1 - k1_min) / dk)), dims[0] - 1);
+  const int imu = std::min(int(std::floor((mu - 0.5) / dmu)), dims[1] - 1);
+  const int it = std::min(int(std::floor((tt - 0.5) / dt)), dims[2] - 1);
+  return (ik * dims[1] + imu) * dims[2] + it;
+}
+
 }  // namespace
 
 int count_lm(int l_max, int m_max, bool even_only) {
@@ -60,7 +72,7 @@ int count_lm(int l_max, int m_max, bool even_only) {
 }
 
 std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out, const Model* model,
-                         bool geometry_only) {
+                         bool geometry_only, const std::vector<std::array<int, 3>>& extra_bins) {
   Tables& T = *out;
   T = Tables();
   T.bin = b;
@@ -219,10 +231,20 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     nlm_norm[j] = norm_lm(T.lm_l[j], T.lm_m[j]);
     pref[j] = std::sqrt((2.0 * T.lm_l[j] + 1.0) / (4.0 * M_PI));
   }
-  const int n_bins = b.n_k1 * b.n_mu * b.n_t;
-  const double dk = (b.k1_max - b.k1_min) / double(b.n_k1);
-  const double dmu = 0.5 / double(b.n_mu);
-  const double dt = 0.5 / double(b.n_t);
+  // the resolutions: the binning's own, then the extra ones
+  std::vector<std::array<int, 3>> rdims{{b.n_k1, b.n_mu, b.n_t}};
+  rdims.insert(rdims.end(), extra_bins.begin(), extra_bins.end());
+  const int n_res = int(rdims.size());
+  const int n_extra = n_res - 1;
+  if (n_res > kMaxResolutions) return "too many resolutions";
+  for (const auto& d : rdims)
+    if (d[0] < 1 || d[1] < 1 || d[2] < 1) return "bin counts must be >= 1";
+  T.res.assign(n_res, Resolution());
+  for (int r = 0; r < n_res; ++r) {
+    T.res[r].n_k1 = rdims[r][0];
+    T.res[r].n_mu = rdims[r][1];
+    T.res[r].n_t = rdims[r][2];
+  }
 
   // ---- canonical plane triples (a, b, -(a+b)), a >= b >= 0, and their kept combinations.
   // The partner with every n negated has conjugate S and, for even l, the same
@@ -244,6 +266,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     int64_t ntri;
   };
   std::vector<std::vector<ComboRec>> per_pt(pts.size());
+  std::vector<std::vector<int32_t>> per_pt_xbin(pts.size());  // bins in the extra resolutions
   std::vector<std::vector<double>> per_pt_w(pts.size()), per_pt_d(pts.size()), per_pt_kmt(pts.size());
   std::vector<std::vector<double>> per_pt_model(model ? pts.size() : 0);
 
@@ -282,13 +305,8 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
               double mu = ((qs[0] + qs[1]) - qs[2]) / ((2.0 * k1) * k2);
               mu = std::min(std::max(mu, -1.0), 1.0);
               if (!(k1 >= b.k1_min && k1 < b.k1_max && tt >= 0.5 && tt <= 1.0 && mu >= 0.5 && mu <= 1.0)) continue;
-              int ik = int(std::floor((k1 - b.k1_min) / dk));
-              ik = std::min(ik, b.n_k1 - 1);
-              int imu = int(std::floor((mu - 0.5) / dmu));
-              imu = std::min(imu, b.n_mu - 1);
-              int it = int(std::floor((tt - 0.5) / dt));
-              it = std::min(it, b.n_t - 1);
-              const int bin = (ik * b.n_mu + imu) * b.n_t + it;
+              const int bin = bin_index(b.k1_min, b.k1_max, rdims[0], k1, mu, tt);
+              for (int r = 1; r < n_res; ++r) per_pt_xbin[ip].push_back(bin_index(b.k1_min, b.k1_max, rdims[r], k1, mu, tt));
 
               // orientation weights, averaged over labellings consistent with k1 >= k2 >= k3
               static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
@@ -355,50 +373,62 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   }
   for (auto& x : th) x.join();
 
-  // ---- per-bin geometry sums (den, counts, means) in a fixed order
-  T.bin_count.assign(n_bins, 0);
-  T.bin_den.assign(size_t(nlm) * n_bins, 0.0);
-  std::vector<double> mean_acc(size_t(n_bins) * 3, 0.0), mean_w(n_bins, 0.0);
-  std::vector<double> model_num(model ? size_t(nlm) * n_bins : 0, 0.0);
+  // ---- per-bin geometry sums (den, counts, means) of every resolution, each in the same fixed order
   int64_t total = 0;
   for (size_t ip = 0; ip < pts.size(); ++ip) {
     if (!per_pt[ip].empty()) T.n_canonical_planes += 1;
-    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
-      const ComboRec& cr = per_pt[ip][i];
-      const double wgt = double(cr.mult) * double(cr.ntri);
-      T.bin_count[cr.bin] += int64_t(cr.mult) * cr.ntri;
-      for (int j = 0; j < nlm; ++j) T.bin_den[size_t(j) * n_bins + cr.bin] += wgt * per_pt_d[ip][i * nlm + j];
-      for (int k = 0; k < 3; ++k) mean_acc[size_t(cr.bin) * 3 + k] += wgt * per_pt_kmt[ip][i * 3 + k];
-      mean_w[cr.bin] += wgt;
-      if (model)
-        for (int j = 0; j < nlm; ++j)
-          // the model is the same on both partners, whose odd-l weights cancel
-          if (T.lm_l[j] % 2 == 0)
-            model_num[size_t(j) * n_bins + cr.bin] += wgt * per_pt_w[ip][i * nlm + j] * per_pt_model[ip][i];
+    for (const ComboRec& cr : per_pt[ip]) {
       if (cr.mult == 1) T.n_self_partner += 1;
       ++total;
     }
   }
   T.n_combos = total;
+  auto bin_of = [&](int r, size_t ip, size_t i) -> int {
+    return r == 0 ? per_pt[ip][i].bin : per_pt_xbin[ip][i * n_extra + (r - 1)];
+  };
+  for (int r = 0; r < n_res; ++r) {
+    Resolution& R = T.res[r];
+    const int n_bins = R.n_bins();
+    R.bin_count.assign(n_bins, 0);
+    R.bin_den.assign(size_t(nlm) * n_bins, 0.0);
+    std::vector<double> mean_acc(size_t(n_bins) * 3, 0.0), mean_w(n_bins, 0.0);
+    std::vector<double> model_num(model ? size_t(nlm) * n_bins : 0, 0.0);
+    for (size_t ip = 0; ip < pts.size(); ++ip) {
+      for (size_t i = 0; i < per_pt[ip].size(); ++i) {
+        const ComboRec& cr = per_pt[ip][i];
+        const int bin = bin_of(r, ip, i);
+        const double wgt = double(cr.mult) * double(cr.ntri);
+        R.bin_count[bin] += int64_t(cr.mult) * cr.ntri;
+        for (int j = 0; j < nlm; ++j) R.bin_den[size_t(j) * n_bins + bin] += wgt * per_pt_d[ip][i * nlm + j];
+        for (int k = 0; k < 3; ++k) mean_acc[size_t(bin) * 3 + k] += wgt * per_pt_kmt[ip][i * 3 + k];
+        mean_w[bin] += wgt;
+        if (model)
+          for (int j = 0; j < nlm; ++j)
+            // the model is the same on both partners, whose odd-l weights cancel
+            if (T.lm_l[j] % 2 == 0)
+              model_num[size_t(j) * n_bins + bin] += wgt * per_pt_w[ip][i * nlm + j] * per_pt_model[ip][i];
+      }
+    }
+    R.bin_mean.assign(size_t(n_bins) * 3, std::nan(""));
+    for (int i = 0; i < n_bins; ++i)
+      if (mean_w[i] > 0)
+        for (int k = 0; k < 3; ++k) R.bin_mean[size_t(i) * 3 + k] = mean_acc[size_t(i) * 3 + k] / mean_w[i];
+    R.bin_empty_lm.assign(size_t(nlm) * n_bins, 0);
+    for (int j = 0; j < nlm; ++j)
+      for (int i = 0; i < n_bins; ++i)
+        R.bin_empty_lm[size_t(j) * n_bins + i] = (R.bin_count[i] == 0 || R.bin_den[size_t(j) * n_bins + i] == 0.0);
+    if (model) {
+      // [B]_d = sqrt((2l+1)/4pi) sum w N_tri B / sum |Y|^2 N_tri (Eq. 13 with B in place of the estimate)
+      R.model_pred.assign(size_t(nlm) * n_bins, std::nan(""));
+      for (int j = 0; j < nlm; ++j)
+        for (int i = 0; i < n_bins; ++i)
+          if (!R.bin_empty_lm[size_t(j) * n_bins + i])
+            R.model_pred[size_t(j) * n_bins + i] = pref[j] * model_num[size_t(j) * n_bins + i] / R.bin_den[size_t(j) * n_bins + i];
+    }
+  }
   for (size_t ip = 0; ip < pts.size(); ++ip) {
     std::vector<double>().swap(per_pt_d[ip]);
     std::vector<double>().swap(per_pt_kmt[ip]);
-  }
-  T.bin_mean.assign(size_t(n_bins) * 3, std::nan(""));
-  for (int i = 0; i < n_bins; ++i)
-    if (mean_w[i] > 0)
-      for (int k = 0; k < 3; ++k) T.bin_mean[size_t(i) * 3 + k] = mean_acc[size_t(i) * 3 + k] / mean_w[i];
-  T.bin_empty_lm.assign(size_t(nlm) * n_bins, 0);
-  for (int j = 0; j < nlm; ++j)
-    for (int i = 0; i < n_bins; ++i)
-      T.bin_empty_lm[size_t(j) * n_bins + i] = (T.bin_count[i] == 0 || T.bin_den[size_t(j) * n_bins + i] == 0.0);
-  if (model) {
-    // [B]_d = sqrt((2l+1)/4pi) sum w N_tri B / sum |Y|^2 N_tri (Eq. 13 with B in place of the estimate)
-    T.model_pred.assign(size_t(nlm) * n_bins, std::nan(""));
-    for (int j = 0; j < nlm; ++j)
-      for (int i = 0; i < n_bins; ++i)
-        if (!T.bin_empty_lm[size_t(j) * n_bins + i])
-          T.model_pred[size_t(j) * n_bins + i] = pref[j] * model_num[size_t(j) * n_bins + i] / T.bin_den[size_t(j) * n_bins + i];
   }
   if (geometry_only) return "";
 
@@ -694,51 +724,62 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
     for (auto& g : T.group_sides) g = remap[g & low] | (g & ~low);
   }
 
-  // ---- per-combination coefficients in bin order (counting sort, stable in pt order)
-  T.bin_ptr.assign(n_bins + 1, 0);
-  for (size_t ip = 0; ip < pts.size(); ++ip)
-    for (const ComboRec& cr : per_pt[ip]) T.bin_ptr[cr.bin + 1] += 1;
-  for (int i = 0; i < n_bins; ++i) T.bin_ptr[i + 1] += T.bin_ptr[i];
-  std::vector<int64_t> fill(T.bin_ptr.begin(), T.bin_ptr.end() - 1);
-  T.combo_bin.resize(total);
-  T.combo_slot.resize(total);
-  T.combo_coef.resize(size_t(total) * nlm);
+  // ---- per-combination coefficients of every resolution in its bin order
+  // (counting sort, stable in pt order)
+  std::vector<std::vector<int64_t>> fill(n_res);
+  for (int r = 0; r < n_res; ++r) {
+    Resolution& R = T.res[r];
+    const int n_bins = R.n_bins();
+    R.bin_ptr.assign(n_bins + 1, 0);
+    for (size_t ip = 0; ip < pts.size(); ++ip)
+      for (size_t i = 0; i < per_pt[ip].size(); ++i) R.bin_ptr[bin_of(r, ip, i) + 1] += 1;
+    for (int i = 0; i < n_bins; ++i) R.bin_ptr[i + 1] += R.bin_ptr[i];
+    fill[r].assign(R.bin_ptr.begin(), R.bin_ptr.end() - 1);
+    R.combo_slot.resize(total);
+    R.combo_coef.resize(size_t(total) * nlm);
+  }
   for (size_t ip = 0; ip < pts.size(); ++ip) {
-    for (size_t i = 0; i < per_pt[ip].size(); ++i) {
-      const ComboRec& cr = per_pt[ip][i];
-      const int64_t pos = fill[cr.bin]++;
-      const double mg = double(T.grid_sizes[cr.level]);
-      const double grid_scale = (double(ng) * double(ng)) / (mg * mg);  // S on the m-grid is (m/N_g)^2 S
-      T.combo_bin[pos] = cr.bin;
-      T.combo_slot[pos] = pt_combo_slot[ip][i];
-      for (int j = 0; j < nlm; ++j) {
-        const double den = T.bin_den[size_t(j) * n_bins + cr.bin];
-        T.combo_coef[size_t(pos) * nlm + j] =
-            den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den * grid_scale : 0.0;
+    for (int r = 0; r < n_res; ++r) {
+      Resolution& R = T.res[r];
+      const int n_bins = R.n_bins();
+      for (size_t i = 0; i < per_pt[ip].size(); ++i) {
+        const ComboRec& cr = per_pt[ip][i];
+        const int bin = bin_of(r, ip, i);
+        const int64_t pos = fill[r][bin]++;
+        const double mg = double(T.grid_sizes[cr.level]);
+        const double grid_scale = (double(ng) * double(ng)) / (mg * mg);  // S on the m-grid is (m/N_g)^2 S
+        R.combo_slot[pos] = pt_combo_slot[ip][i];
+        for (int j = 0; j < nlm; ++j) {
+          const double den = R.bin_den[size_t(j) * n_bins + bin];
+          R.combo_coef[size_t(pos) * nlm + j] =
+              den > 0 ? pref[j] * double(cr.mult) * per_pt_w[ip][i * nlm + j] / den * grid_scale : 0.0;
+        }
       }
     }
     std::vector<ComboRec>().swap(per_pt[ip]);
+    std::vector<int32_t>().swap(per_pt_xbin[ip]);
     std::vector<double>().swap(per_pt_w[ip]);
     std::vector<int64_t>().swap(pt_combo_slot[ip]);
   }
   // within each bin, order the combinations by output slot (locality of the S gather)
-  {
-    std::vector<int64_t> idx;
-    std::vector<int64_t> tmp_slot;
-    std::vector<double> tmp_coef;
-    for (int bin = 0; bin < n_bins; ++bin) {
-      const int64_t c0 = T.bin_ptr[bin], c1 = T.bin_ptr[bin + 1];
+  std::vector<int64_t> idx;
+  std::vector<int64_t> tmp_slot;
+  std::vector<double> tmp_coef;
+  for (int r = 0; r < n_res; ++r) {
+    Resolution& R = T.res[r];
+    for (int bin = 0; bin < R.n_bins(); ++bin) {
+      const int64_t c0 = R.bin_ptr[bin], c1 = R.bin_ptr[bin + 1];
       if (c1 - c0 < 2) continue;
       idx.resize(c1 - c0);
       for (int64_t i = 0; i < c1 - c0; ++i) idx[i] = c0 + i;
-      std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return T.combo_slot[x] < T.combo_slot[y]; });
+      std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return R.combo_slot[x] < R.combo_slot[y]; });
       tmp_slot.resize(c1 - c0);
-      for (int64_t i = 0; i < c1 - c0; ++i) tmp_slot[i] = T.combo_slot[idx[i]];
-      std::copy(tmp_slot.begin(), tmp_slot.end(), T.combo_slot.begin() + c0);
+      for (int64_t i = 0; i < c1 - c0; ++i) tmp_slot[i] = R.combo_slot[idx[i]];
+      std::copy(tmp_slot.begin(), tmp_slot.end(), R.combo_slot.begin() + c0);
       tmp_coef.resize(size_t(c1 - c0) * nlm);
       for (int64_t i = 0; i < c1 - c0; ++i)
-        for (int j = 0; j < nlm; ++j) tmp_coef[size_t(i) * nlm + j] = T.combo_coef[size_t(idx[i]) * nlm + j];
-      std::copy(tmp_coef.begin(), tmp_coef.end(), T.combo_coef.begin() + size_t(c0) * nlm);
+        for (int j = 0; j < nlm; ++j) tmp_coef[size_t(i) * nlm + j] = R.combo_coef[size_t(idx[i]) * nlm + j];
+      std::copy(tmp_coef.begin(), tmp_coef.end(), R.combo_coef.begin() + size_t(c0) * nlm);
     }
   }
   return "";

@@ -4,6 +4,7 @@
 // a kept combination) is taken in plain IEEE operations in a fixed order.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -62,6 +63,23 @@ struct ItemDesc {
   uint8_t b_slot[kTileN];
 };
 
+constexpr int kMaxResolutions = 8;
+
+// One second-level binning of the kept combinations (Eq. 13): the same k1
+// range, (l, m) outputs and combinations, with its own numbers of bins.
+struct Resolution {
+  int n_k1 = 0, n_mu = 0, n_t = 0;
+  std::vector<int64_t> combo_slot;       // per combination in bin order: index into the K3 output (item * cells + pair * 16 + col)
+  std::vector<double> combo_coef;        // [combo][n_lm]: final coefficient on Re S (Im S for odd l)
+  std::vector<int64_t> bin_ptr;          // combinations sorted by bin: CSR offsets [n_bins + 1]
+  std::vector<int64_t> bin_count;        // sum of mult * N_tri per bin
+  std::vector<double> bin_den;           // [n_lm][n_bins]
+  std::vector<double> bin_mean;          // [n_bins][3]
+  std::vector<uint8_t> bin_empty_lm;     // [n_lm][n_bins] 1 if NaN
+  std::vector<double> model_pred;        // [n_lm][n_bins] discrete prediction (with a model), NaN if empty
+  int n_bins() const { return n_k1 * n_mu * n_t; }
+};
+
 struct Tables {
   Binning bin;
   K3Shape k3;
@@ -84,15 +102,9 @@ struct Tables {
   int64_t n_combos = 0;
   int64_t n_self_partner = 0;             // combinations equal to their n -> -n partner
   int64_t n_canonical_planes = 0;
-  std::vector<int32_t> combo_bin;        // per combination
-  std::vector<int64_t> combo_slot;       // index into the K3 output (item * pairs * 16 + pair * 16 + col)
-  std::vector<double> combo_coef;        // [combo][n_lm]: final coefficient on Re S
-  std::vector<int64_t> bin_ptr;          // combinations sorted by bin: CSR offsets [n_bins + 1]
-  std::vector<int64_t> bin_count;        // sum of mult * N_tri per bin
-  std::vector<double> bin_den;           // [n_lm][n_bins]
-  std::vector<double> bin_mean;          // [n_bins][3]
-  std::vector<uint8_t> bin_empty_lm;     // [n_lm][n_bins] 1 if NaN
-  std::vector<double> model_pred;        // [n_lm][n_bins] discrete prediction (with a model), NaN if empty
+  // the second-level binnings: res[0] is the binning's own (n_k1, n_mu, n_t),
+  // further ones share everything but the bin counts
+  std::vector<Resolution> res;
 
   // x_perp grids.  A combination of rings whose modes reach |u_x|, |u_y| <= U
   // is summed exactly on any m x m grid with m > U_A + U_B + U_C (no closure
@@ -128,8 +140,11 @@ struct Model {
 // Builds everything; returns "" on success or an error message.  With a
 // model, also the discrete prediction [B]_d per bin (model_pred).  With
 // geometry_only, stops after the per-bin geometry (no contraction tables).
+// extra_bins lists further (n_k1, n_mu, n_t) binnings of the same
+// combinations (res[1], res[2], ...).
 std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tables* out,
-                         const Model* model = nullptr, bool geometry_only = false);
+                         const Model* model = nullptr, bool geometry_only = false,
+                         const std::vector<std::array<int, 3>>& extra_bins = {});
 
 // [B_l^m]_c / B_r for the model's redshift-space factor (Eq. 4 with Eqs. 3
 // and 17), by Gauss-Legendre x uniform-phase quadrature, exact for the
