@@ -203,22 +203,40 @@ def estimate(delta: np.ndarray, binning: Binning, method: str = "fft", geom: Geo
 
 def _stream_chunk(task):
     """Worker: Eq. 8 sums and Eq. 13 accumulators for one set of plane triples."""
-    delta, binning, rings, ntri, sides, triples = task
-    num, den, counts, _ = stream_plane_triples(delta, binning, rings, ntri, sides, triples)
-    return num, den, counts
+    delta, binnings, rings, ntri, sides, triples = task
+    return stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples)[0]
 
 
 def stream_plane_triples(delta, binning, rings, ntri, sides, triples):
     """Eq. 8 sums and Eq. 13 accumulators (num, den, counts) over the given
     plane triples, plus the number of combinations visited."""
-    from .geometry import Combos, Geometry, combos_for_planes
+    parts, n_visited = stream_plane_triples_binnings(delta, [binning], rings, ntri, sides, triples)
+    return parts[0] + (n_visited,)
 
+
+def _same_combinations(binnings):
+    """The kept combinations depend on the k1 range, the grid and the (l, m)
+    list only; the bin counts decide nothing but the bin index."""
+    b0 = binnings[0]
+    for b in binnings[1:]:
+        if (b.ng, b.k1_min, b.k1_max, b.length, b.l_max, b.m_max, b.even_l_only) != (
+                b0.ng, b0.k1_min, b0.k1_max, b0.length, b0.l_max, b0.m_max, b0.even_l_only):
+            raise ValueError("binnings may differ in n_k1, n_mu and n_t only")
+
+
+def stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples):
+    """As ``stream_plane_triples`` for several second-level binnings of the
+    same combinations: each combination's T is computed once and added to the
+    bin it falls in under every binning.  Returns ([(num, den, counts) per
+    binning], combinations visited)."""
+    from .geometry import Combos, Geometry, _bin_index, combos_for_planes
+
+    _same_combinations(binnings)
+    binning = binnings[0]
     n_visited = 0
-    nb = binning.n_bins
     nlm = len(binning.lms())
-    num = np.zeros((nlm, nb), dtype=np.complex128)
-    den = np.zeros((nlm, nb))
-    counts = np.zeros(nb, dtype=np.int64)
+    acc = [(np.zeros((nlm, b.n_bins), dtype=np.complex128), np.zeros((nlm, b.n_bins)),
+            np.zeros(b.n_bins, dtype=np.int64)) for b in binnings]
     Delta = fourier_field(delta, binning.box_len)
     for pt in triples:
         res = combos_for_planes(rings, ntri, sides, binning, *pt)
@@ -228,11 +246,13 @@ def stream_plane_triples(delta, binning, rings, ntri, sides, triples):
         n_visited += len(combos.ntri)
         geom = Geometry(binning, rings, ntri, sides, combos)
         T = triple_sums_fft(geom, Delta)
-        for j in range(nlm):
-            np.add.at(num[j], combos.bin, combos.w[:, j] * T)
-            np.add.at(den[j], combos.bin, combos.d[:, j] * combos.ntri.astype(np.float64))
-        np.add.at(counts, combos.bin, combos.ntri)
-    return num, den, counts, n_visited
+        for b, (num, den, counts) in zip(binnings, acc):
+            bins = _bin_index(b, combos.k1, combos.mu, combos.t)
+            for j in range(nlm):
+                np.add.at(num[j], bins, combos.w[:, j] * T)
+                np.add.at(den[j], bins, combos.d[:, j] * combos.ntri.astype(np.float64))
+            np.add.at(counts, bins, combos.ntri)
+    return acc, n_visited
 
 
 def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, chunks: int = 64) -> Multipoles:
@@ -244,14 +264,23 @@ def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, ch
     triples are split into ``chunks`` groups, optionally over ``workers``
     processes; the partial sums are added in chunk order.
     """
+    return estimate_streaming_binnings(delta, [binning], workers, chunks)[0]
+
+
+def estimate_streaming_binnings(delta: np.ndarray, binnings, workers: int = 1, chunks: int = 64) -> list:
+    """``estimate_streaming`` for several second-level binnings (Eq. 13 at
+    several (mu, t) resolutions, Sec. III.D) that differ in their bin counts
+    only: one Multipoles per binning, each equal to a separate run."""
     from .geometry import make_rings, make_sides, plane_triples, triangle_counts
 
+    binning = binnings[0]
+    _same_combinations(binnings)
     rings = make_rings(binning.ng)
     ntri = triangle_counts(rings)
     sides = make_sides(rings, binning)
     triples = plane_triples(int(math.ceil(binning.k1_max)))
     groups = [triples[i::chunks] for i in range(chunks)]
-    tasks = [(delta, binning, rings, ntri, sides, g) for g in groups if g]
+    tasks = [(delta, list(binnings), rings, ntri, sides, g) for g in groups if g]
     if workers > 1:
         import multiprocessing as mp
 
@@ -259,17 +288,21 @@ def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, ch
             parts = pool.map(_stream_chunk, tasks, chunksize=1)
     else:
         parts = [_stream_chunk(t) for t in tasks]
-    nb = binning.n_bins
     lms = binning.lms()
-    num = np.zeros((len(lms), nb), dtype=np.complex128)
-    den = np.zeros((len(lms), nb))
-    counts = np.zeros(nb, dtype=np.int64)
-    for pnum, pden, pc in parts:
-        num += pnum
-        den += pden
-        counts += pc
-    B = _finish(lms, num, den)
-    B[:, counts == 0] = np.nan
-    B[den == 0.0] = np.nan
-    shape = (len(lms), binning.n_k1, binning.n_mu, binning.n_t)
-    return Multipoles(lms, B.reshape(shape), counts.reshape(shape[1:]), num, den)
+    out = []
+    for ib, b in enumerate(binnings):
+        nb = b.n_bins
+        num = np.zeros((len(lms), nb), dtype=np.complex128)
+        den = np.zeros((len(lms), nb))
+        counts = np.zeros(nb, dtype=np.int64)
+        for part in parts:
+            pnum, pden, pc = part[ib]
+            num += pnum
+            den += pden
+            counts += pc
+        B = _finish(lms, num, den)
+        B[:, counts == 0] = np.nan
+        B[den == 0.0] = np.nan
+        shape = (len(lms), b.n_k1, b.n_mu, b.n_t)
+        out.append(Multipoles(lms, B.reshape(shape), counts.reshape(shape[1:]), num, den))
+    return out

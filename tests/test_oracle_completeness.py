@@ -226,3 +226,24 @@ def test_bin_counts_at_the_paper_validation_setup():
     for i in range(12):
         row = counts[i][full[i]]
         assert np.all(np.diff(row) > -0.1 * row[:-1]), (i, row)
+
+
+def test_several_binnings_equal_separate_runs():
+    """The oracle's multi-resolution streaming (one T per combination, binned
+    under every binning) equals one plain estimate per binning."""
+    from oracle.estimator import estimate, estimate_streaming_binnings
+    from synth import FieldRecipe, make_field
+
+    delta = make_field(FieldRecipe(24, n_s=-2.0, f_ng=0.5, beta=0.5, seed=3))
+    bs = [Binning(24, 2, 2.0, 8.0, 3, 3), Binning(24, 1, 2.0, 8.0, 5, 2), Binning(24, 3, 2.0, 8.0, 2, 4)]
+    multi = estimate_streaming_binnings(delta, bs, workers=1, chunks=5)
+    for b, got in zip(bs, multi):
+        ref = estimate(delta, b)
+        assert np.array_equal(got.counts, ref.counts)
+        ok = ~np.isnan(ref.B)
+        assert np.array_equal(~np.isnan(got.B), ok)
+        assert ok.any()
+        scale = np.max(np.abs(ref.B[ok]))
+        assert np.max(np.abs(got.B[ok] - ref.B[ok])) < 1e-12 * scale
+    with pytest.raises(ValueError):
+        estimate_streaming_binnings(delta, [bs[0], Binning(24, 2, 2.0, 7.0, 3, 3)])
