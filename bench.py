@@ -167,9 +167,11 @@ def cpu_baseline(delta64, ng, wl, info):
         "unit": "bin-multipoles/s",
         "cores": int(cores),
         "kind": "oracle",
-        "sample": (f"float64 oracle (numpy FFT + BLAS contraction) on every {stride}th of {len(triples)} plane "
-                   f"triples: {n_visited} of {int(total)} combinations in {t_sample:.1f} s, plus {t_setup:.1f} s "
-                   f"of ring/N_tri setup; projected full estimate {t_full:.0f} s"),
+        "projected": True,
+        "sample": (f"PROJECTED from a sample: float64 oracle (numpy FFT + BLAS contraction) on every {stride}th of "
+                   f"{len(triples)} plane triples, {n_visited} of {int(total)} combinations (both n -> -n partners "
+                   f"counted, as the oracle visits them) in {t_sample:.1f} s, plus {t_setup:.1f} s of ring/N_tri "
+                   f"setup; projected full estimate {t_full:.0f} s"),
     }
 
 

@@ -7,6 +7,7 @@ B [n_lm][n_k1][n_mu][n_t] (NaN where empty), the triangle counts, the (l, m)
 list, the binning and recipe, and the SHA-256 of the generated field so a test
 can confirm it regenerated the same input.
 """
+import math
 import os
 import sys
 import time
@@ -25,6 +26,9 @@ from synth import FieldRecipe, field_digest, make_field  # noqa: E402
 #   ng128_all_l   the N_g = 128 workload with every l <= 6 (odd l from the imaginary part)
 #   ng96          the first N_g = 96 field of the uneven batch (seed 24; 20 k1 on [1, 32), 10 x 10)
 #   ng192         N_g = 192, 20 k1 shells on [1, 64), 10 mu x 10 t, seed 0
+#   val384        the validation setup of Sec. III.B-D: N_g = 384, L = 215 Mpc,
+#                 k1 = 2.1 +- 0.1 Mpc^-1, 12 mu x 12 t, beta = 1, seed 1000
+KF_VAL = 2.0 * math.pi / 215.0  # fundamental mode of the validation box, Mpc^-1
 CONFIGS = {
     "ng128": (Binning(128, 20, 1.0, 128 / 3, 10, 10), FieldRecipe(128, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
     "ng256": (Binning(256, 40, 1.0, 256 / 3, 20, 10), FieldRecipe(256, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
@@ -32,6 +36,8 @@ CONFIGS = {
                     FieldRecipe(128, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
     "ng96": (Binning(96, 20, 1.0, 32.0, 10, 10), FieldRecipe(96, n_s=-2.0, f_ng=0.5, beta=0.5, seed=24)),
     "ng192": (Binning(192, 20, 1.0, 64.0, 10, 10), FieldRecipe(192, n_s=-2.0, f_ng=0.5, beta=0.5, seed=0)),
+    "val384": (Binning(384, 1, 2.0 / KF_VAL, 2.2 / KF_VAL, 12, 12, box_len=215.0),
+               FieldRecipe(384, box_len=215.0, n_s=-2.0, f_ng=0.5, beta=1.0, seed=1000)),
 }
 
 
@@ -47,8 +53,8 @@ def main(names):
             B=res.B,
             counts=res.counts,
             lms=np.array(res.lms),
-            binning=np.array([b.ng, b.n_k1, b.k1_min, b.k1_max, b.n_mu, b.n_t, int(b.even_l_only)]),
-            recipe=np.array([rec.ng, rec.n_s, rec.f_ng, rec.beta, rec.sigma_g, rec.seed]),
+            binning=np.array([b.ng, b.n_k1, b.k1_min, b.k1_max, b.n_mu, b.n_t, int(b.even_l_only), b.length]),
+            recipe=np.array([rec.ng, rec.n_s, rec.f_ng, rec.beta, rec.sigma_g, rec.seed, rec.length]),
             digest=np.array(field_digest(delta)),
         )
         print(f"{name}: wrote {out} in {time.time() - t0:.0f} s", flush=True)

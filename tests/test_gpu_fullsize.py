@@ -111,3 +111,55 @@ def test_fullsize_every_l(ng, prec):
         worst = max(worst, np.max(np.abs(Bf[j][okj] + B[j][okj])) / scale)
     print(f"  odd-l reflection residual {worst:.3e}", flush=True)
     assert worst < tol
+
+
+@pytest.fixture(scope="module")
+def val384_field():
+    gold = np.load(os.path.join(HERE, "golden", "oracle_val384.npz"))
+    ng, n_s, f_ng, beta, _, seed, box = gold["recipe"]
+    print("validation-setup field: generating N_g = 384 on the host", flush=True)
+    delta = make_field(FieldRecipe(int(ng), box_len=float(box), n_s=float(n_s), f_ng=float(f_ng), beta=float(beta),
+                                   seed=int(seed)))
+    assert field_digest(delta) == str(gold["digest"]), "regenerated field differs from the stored one"
+    return gold, delta
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_validation_setup_against_stored_oracle(val384_field, prec):
+    """The paper's validation configuration (N_g = 384, L = 215 Mpc,
+    k1 = 2.1 +- 0.1 Mpc^-1, 12 x 12 (mu, t) bins, l <= 6) on one realisation,
+    element by element against the stored float64 oracle, through a
+    three-resolution plan (12 x 12, 8 x 8, 6 x 6) whose first resolution is
+    the stored binning."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_14513_amd import bk
+
+    gold, delta = val384_field
+    ng, n_k1, k1_min, k1_max, n_mu, n_t, even, box = gold["binning"]
+    print(f"validation-setup parity prec={prec}", flush=True)
+    b = bk.make_binning(int(ng), int(n_k1), float(k1_min), float(k1_max), int(n_mu), int(n_t), box_len=float(box),
+                        even_l_only=int(even))
+    est = bk.Estimator(b, prec=prec, extra_bins=[(1, 8, 8), (1, 6, 6)])
+    try:
+        t = torch.from_numpy(delta.astype(np.float32) if prec == 1 else delta).cuda()
+        s = torch.cuda.current_stream().cuda_stream
+        est.load(t, s)
+        est.estimate(s)
+        B = est.multipoles(0)[0]
+        counts = est.counts(0)
+        lms = est.lm_list()
+    finally:
+        est.close()
+    assert [tuple(x) for x in gold["lms"].tolist()] == lms
+    assert np.array_equal(counts, gold["counts"])
+    ref = gold["B"]
+    assert np.array_equal(np.isnan(B), np.isnan(ref))
+    nlm = ref.shape[0]
+    Bf, rf = B.reshape(nlm, -1), ref.reshape(nlm, -1)
+    ok = ~np.isnan(rf)
+    err = np.array([np.max(np.abs(Bf[j][ok[j]] - rf[j][ok[j]])) / np.max(np.abs(rf[j][ok[j]])) for j in range(nlm)])
+    print(f"  max error per multipole {err.max():.3e}", flush=True)
+    assert err.max() < (1e-11 if prec == 2 else 1e-5), err
