@@ -203,8 +203,8 @@ def estimate(delta: np.ndarray, binning: Binning, method: str = "fft", geom: Geo
 
 def _stream_chunk(task):
     """Worker: Eq. 8 sums and Eq. 13 accumulators for one set of plane triples."""
-    delta, binnings, rings, ntri, sides, triples = task
-    return stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples)[0]
+    delta, binnings, rings, ntri, sides, triples, bins = task
+    return stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples, bins)[0]
 
 
 def stream_plane_triples(delta, binning, rings, ntri, sides, triples):
@@ -224,11 +224,13 @@ def _same_combinations(binnings):
             raise ValueError("binnings may differ in n_k1, n_mu and n_t only")
 
 
-def stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples):
+def stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples, bins=None):
     """As ``stream_plane_triples`` for several second-level binnings of the
     same combinations: each combination's T is computed once and added to the
-    bin it falls in under every binning.  Returns ([(num, den, counts) per
-    binning], combinations visited)."""
+    bin it falls in under every binning.  With ``bins`` (flat bin indices of
+    the first binning), only the combinations in those bins are summed, so
+    only those bins are complete.  Returns ([(num, den, counts) per binning],
+    combinations visited)."""
     from .geometry import Combos, Geometry, _bin_index, combos_for_planes
 
     _same_combinations(binnings)
@@ -243,15 +245,20 @@ def stream_plane_triples_binnings(delta, binnings, rings, ntri, sides, triples):
         if res is None:
             continue
         combos = Combos(*res)
+        if bins is not None:
+            keep = np.isin(combos.bin, bins)
+            if not keep.any():
+                continue
+            combos = Combos(*(a[keep] for a in res))
         n_visited += len(combos.ntri)
         geom = Geometry(binning, rings, ntri, sides, combos)
         T = triple_sums_fft(geom, Delta)
         for b, (num, den, counts) in zip(binnings, acc):
-            bins = _bin_index(b, combos.k1, combos.mu, combos.t)
+            idx = _bin_index(b, combos.k1, combos.mu, combos.t)
             for j in range(nlm):
-                np.add.at(num[j], bins, combos.w[:, j] * T)
-                np.add.at(den[j], bins, combos.d[:, j] * combos.ntri.astype(np.float64))
-            np.add.at(counts, bins, combos.ntri)
+                np.add.at(num[j], idx, combos.w[:, j] * T)
+                np.add.at(den[j], idx, combos.d[:, j] * combos.ntri.astype(np.float64))
+            np.add.at(counts, idx, combos.ntri)
     return acc, n_visited
 
 
@@ -267,10 +274,16 @@ def estimate_streaming(delta: np.ndarray, binning: Binning, workers: int = 1, ch
     return estimate_streaming_binnings(delta, [binning], workers, chunks)[0]
 
 
-def estimate_streaming_binnings(delta: np.ndarray, binnings, workers: int = 1, chunks: int = 64) -> list:
+def estimate_streaming_binnings(delta: np.ndarray, binnings, workers: int = 1, chunks: int = 64, bins=None,
+                                plane_filter=None) -> list:
     """``estimate_streaming`` for several second-level binnings (Eq. 13 at
     several (mu, t) resolutions, Sec. III.D) that differ in their bin counts
-    only: one Multipoles per binning, each equal to a separate run."""
+    only: one Multipoles per binning, each equal to a separate run.
+
+    Sampling a grid too large for a full run: ``bins`` restricts the sums to
+    the combinations of those bins of the first binning (the other bins come
+    out incomplete), and ``plane_filter`` (a predicate on plane triples) skips
+    triples that cannot reach them."""
     from .geometry import make_rings, make_sides, plane_triples, triangle_counts
 
     binning = binnings[0]
@@ -279,8 +292,11 @@ def estimate_streaming_binnings(delta: np.ndarray, binnings, workers: int = 1, c
     ntri = triangle_counts(rings)
     sides = make_sides(rings, binning)
     triples = plane_triples(int(math.ceil(binning.k1_max)))
+    if plane_filter is not None:
+        triples = [pt for pt in triples if plane_filter(pt)]
     groups = [triples[i::chunks] for i in range(chunks)]
-    tasks = [(delta, list(binnings), rings, ntri, sides, g) for g in groups if g]
+    bins = None if bins is None else np.asarray(bins, dtype=np.int64)
+    tasks = [(delta, list(binnings), rings, ntri, sides, g, bins) for g in groups if g]
     if workers > 1:
         import multiprocessing as mp
 

@@ -163,3 +163,57 @@ def test_validation_setup_against_stored_oracle(val384_field, prec):
     err = np.array([np.max(np.abs(Bf[j][ok[j]] - rf[j][ok[j]])) / np.max(np.abs(rf[j][ok[j]])) for j in range(nlm)])
     print(f"  max error per multipole {err.max():.3e}", flush=True)
     assert err.max() < (1e-11 if prec == 2 else 1e-5), err
+
+
+@pytest.fixture(scope="module")
+def ng512_field():
+    gold = np.load(os.path.join(HERE, "golden", "oracle_ng512_lowk.npz"))
+    ng, n_s, f_ng, beta, _, seed, box = gold["recipe"]
+    print("N_g = 512 field: generating on the host", flush=True)
+    delta = make_field(FieldRecipe(int(ng), box_len=float(box), n_s=float(n_s), f_ng=float(f_ng), beta=float(beta),
+                                   seed=int(seed)))
+    assert field_digest(delta) == str(gold["digest"]), "regenerated field differs from the stored one"
+    return gold, delta
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_ng512_sampled_bins_against_stored_oracle(ng512_field, prec):
+    """The N_g = 512 workload (60 k1 x 20 mu x 15 t, the bench configuration)
+    against the float64 oracle on the 900 bins of its three lowest k1 shells,
+    the ones the oracle can afford at this size (stored by make_golden.py
+    with the oracle's bin filter)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_14513_amd import bk
+
+    gold, delta = ng512_field
+    ng, n_k1, k1_min, k1_max, n_mu, n_t, even, box = gold["binning"]
+    bins = gold["sampled_bins"]
+    print(f"N_g = 512 sampled-bin parity prec={prec}", flush=True)
+    b = bk.make_binning(int(ng), int(n_k1), float(k1_min), float(k1_max), int(n_mu), int(n_t), box_len=float(box),
+                        even_l_only=int(even))
+    est = bk.Estimator(b, prec=prec)
+    try:
+        t = torch.from_numpy(delta.astype(np.float32) if prec == 1 else delta).cuda()
+        s = torch.cuda.current_stream().cuda_stream
+        est.load(t, s)
+        est.estimate(s)
+        B = est.multipoles()[0]
+        counts = est.counts()
+        lms = est.lm_list()
+        del t
+    finally:
+        est.close()
+    assert [tuple(x) for x in gold["lms"].tolist()] == lms
+    assert np.array_equal(counts.ravel()[bins], gold["counts"].ravel()[bins])
+    nlm = len(lms)
+    Bs, Rs = B.reshape(nlm, -1)[:, bins], gold["B"].reshape(nlm, -1)[:, bins]
+    assert np.array_equal(np.isnan(Bs), np.isnan(Rs))
+    ok = ~np.isnan(Rs)
+    assert ok.sum() > 100 * nlm // 2
+    err = np.array([np.max(np.abs(Bs[j][ok[j]] - Rs[j][ok[j]])) / np.max(np.abs(Rs[j][ok[j]])) for j in range(nlm)])
+    print(f"  max error per multipole over {ok[0].sum()} bins {err.max():.3e}", flush=True)
+    assert err.max() < (1e-11 if prec == 2 else 1e-5), err

@@ -247,3 +247,22 @@ def test_several_binnings_equal_separate_runs():
         assert np.max(np.abs(got.B[ok] - ref.B[ok])) < 1e-12 * scale
     with pytest.raises(ValueError):
         estimate_streaming_binnings(delta, [bs[0], Binning(24, 2, 2.0, 7.0, 3, 3)])
+
+
+def test_bin_sampled_streaming_equals_the_full_estimate():
+    """Restricting the streaming sums to some bins (and the plane triples that
+    can reach them) leaves those bins exactly as the full estimate has them."""
+    from oracle.estimator import estimate, estimate_streaming_binnings
+    from synth import FieldRecipe, make_field
+
+    delta = make_field(FieldRecipe(24, n_s=-2.0, f_ng=0.5, beta=0.5, seed=3))
+    b = Binning(24, 3, 2.0, 8.0, 3, 3)
+    ref = estimate(delta, b)
+    bins = np.arange(9)  # the lowest k1 shell, [2, 4): every side has k < 4
+    got = estimate_streaming_binnings(delta, [b], bins=bins, plane_filter=lambda pt: max(abs(n) for n in pt) < 4.0)[0]
+    B = got.B.reshape(len(got.lms), -1)[:, bins]
+    R = ref.B.reshape(len(ref.lms), -1)[:, bins]
+    ok = ~np.isnan(R)
+    assert ok.any() and np.array_equal(~np.isnan(B), ok)
+    assert np.max(np.abs(B[ok] - R[ok])) < 1e-12 * np.max(np.abs(R[ok]))
+    assert np.array_equal(got.counts.ravel()[bins], ref.counts.ravel()[bins])
