@@ -353,6 +353,9 @@ def main():
     }
     out["plan"] = {k: info[k] for k in ("combinations", "work_items", "sides", "rings", "plane_triples")}
     out["plan"]["tiles"] = info["tiles"]  # [FFT lines, ring-sum columns, slots per chunk]
+    # first-level estimates per second: every combination and its n -> -n partner (one S serves both)
+    first_level = 2 * info["combinations"] - info["self_partnered"]
+    out["first_level_combinations_per_s"] = first_level / (ms32 * 1e-3)
     if not args.no_fp64:
         ms64, st64, B64, info64 = time_path(bk, torch, binning, bk.BK_F64, f64, args.steps, args.warmup,
                                             not args.no_autotune)
