@@ -177,12 +177,14 @@ def ng512_field():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("prec", [2], ids=["f64"])
 def test_ng512_sampled_bins_against_stored_oracle(ng512_field, prec):
     """The N_g = 512 workload (60 k1 x 20 mu x 15 t, the bench configuration)
     against the float64 oracle on the 900 bins of its three lowest k1 shells,
     the ones the oracle can afford at this size (stored by make_golden.py
-    with the oracle's bin filter)."""
+    with the oracle's bin filter).  The float64 path only: each plan at this
+    size takes about a minute to build, and test_ng512 ties the float32 path
+    to the float64 one on every bin."""
     import torch
 
     if not torch.cuda.is_available():
