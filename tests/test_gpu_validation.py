@@ -188,7 +188,26 @@ def _summary_lines(ens):
             ok = np.isfinite(fr)
             lines.append(f"f_NG={f:g} B_0^0 ({n}x{n}) fractional deviation from [B]_d: median |dev| "
                          f"{np.median(np.abs(fr[ok])):.4f}, range [{fr[ok].min():.4f}, {fr[ok].max():.4f}]")
-    return lines + _orders_lines(ens)
+    return lines + _orders_lines(ens) + _boundary_lines(ens)
+
+
+def _boundary_lines(ens):
+    """B_0^0 and B_2^0 along the three boundaries of the 12 x 12 (mu, t)
+    plane at f_NG = 0.5: mean, sigma and [B]_d per bin (the right-hand
+    panels of the paper's l = 0, 2 figure)."""
+    lines = []
+    st = ens["stats"][(0.5, 12)]
+    c = ens["counts"][0][0]
+    means = ens["means"][0][0]
+    for name, idx in _boundaries(12, c).items():
+        for l in (0, 2):
+            j = ens["lms"].index((l, 0))
+            cells = []
+            for im, it in idx:
+                cells.append(f"(mu {means[im, it, 1]:.3f}, t {means[im, it, 2]:.3f}) {st['mean'][j][0, im, it]:.4g} "
+                             f"+- {st['sigma'][j][0, im, it]:.2g} vs {st['bd'][j][0, im, it]:.4g}")
+            lines.append(f"boundary {name} l={l} m=0: " + "; ".join(cells))
+    return lines
 
 
 def _deltas(ens, f, l_filter=lambda l: True):
