@@ -696,9 +696,10 @@ extern "C" bk_status bk_plan_create_multires(const bk_binning* bn, const int* ex
   // slot-B window) rows tightly; two per wave make workgroups of 16 items,
   // which share their staged sides: about 0.26 staged bytes per padded term
   // (float32) against 0.33 with eight items, and the contraction is close to
-  // bound by that traffic.  Two buffers of 151 slots of 256 bytes take
-  // 77 312 bytes of LDS: two workgroups per compute unit.  With one item per
-  // wave, 104 sides (53 760 bytes) let three workgroups share a compute unit.
+  // bound by that traffic.  Two buffers of 160 slots (159 sides and the zero
+  // slot) of 256 bytes take 81 920 bytes of LDS: two workgroups fill the
+  // compute unit's 160 KiB.  With one item per wave, 104 sides (53 760 bytes)
+  // let three workgroups share a compute unit.
   // BK_K3_PAIRS=32 or 64 selects items of two or four tiles (one per wave),
   // BK_K3_ITEMS=1 one 16-pair item per wave; BK_K3_SIDES overrides the cap.
   bk::K3Shape shape;
@@ -709,7 +710,7 @@ extern "C" bk_status bk_plan_create_multires(const bk_binning* bn, const int* ex
     if (shape.pairs_per_item != 16) shape.items_per_wave = 1;
   }
   if (const char* v = std::getenv("BK_K3_ITEMS")) shape.items_per_wave = std::atoi(v);
-  shape.max_group_sides = shape.items_per_wave == 2 ? 150 : 104;
+  shape.max_group_sides = shape.items_per_wave == 2 ? 159 : 104;
   if (const char* v = std::getenv("BK_K3_SIDES")) shape.max_group_sides = std::atoi(v);
   if (const char* v = std::getenv("BK_FULL_GRID")) shape.coarse_grids = std::atoi(v) == 0;
   std::string err;
