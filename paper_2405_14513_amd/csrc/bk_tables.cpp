@@ -570,15 +570,89 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
       if (bu >> j & 1u) out->push_back(side(it.lo + j, bb));
     *b_used = bu;
   };
+  // Items of one grid are ordered into workgroups: a group starts at the
+  // first item not yet placed and repeatedly takes, among the next
+  // kGroupLook unplaced items of the packing order, the one that adds the
+  // fewest sides to the group (the earliest on ties), up to
+  // kWavesPerGroup * ipw items and max_group_sides sides.  Fewer staged sides
+  // per item means less staging traffic per term.  Each candidate's overlap
+  // with the group is kept up to date through per-side lists of the items
+  // that stage the side.
+  constexpr size_t kGroupLook = 16384;
+  auto cluster = [&](const std::vector<PItem>& in, std::vector<PItem>* out, std::vector<size_t>* ends) {
+    const size_t n = in.size();
+    std::vector<std::vector<int32_t>> isides(n);
+    std::map<int32_t, std::vector<int32_t>> holders;  // side -> items staging it, ascending
+    for (size_t i = 0; i < n; ++i) {
+      uint32_t bu = 0;
+      item_sides(in[i], &isides[i], &bu);
+      std::sort(isides[i].begin(), isides[i].end());
+      isides[i].erase(std::unique(isides[i].begin(), isides[i].end()), isides[i].end());
+      for (int32_t x : isides[i]) holders[x].push_back(int32_t(i));
+    }
+    std::vector<char> placed(n, 0);
+    std::vector<int32_t> overlap(n, 0);  // sides an item shares with the current group
+    std::vector<int32_t> members;        // sides of the current group
+    size_t first = 0;
+    while (first < n) {
+      members.clear();
+      size_t nitems = 0;
+      auto take = [&](size_t i) {
+        for (int32_t x : isides[i]) {
+          if (std::find(members.begin(), members.end(), x) != members.end()) continue;
+          members.push_back(x);
+          for (int32_t j : holders[x]) overlap[j] += 1;
+        }
+        placed[i] = 1;
+        out->push_back(in[i]);
+        ++nitems;
+      };
+      take(first);
+      while (nitems < size_t(kWavesPerGroup * ipw)) {
+        size_t best = n, seen = 0;
+        int best_new = 1 << 30;
+        for (size_t j = first + 1; j < n && seen < kGroupLook; ++j) {
+          if (placed[j]) continue;
+          ++seen;
+          const int add = int(isides[j].size()) - overlap[j];
+          if (add >= best_new || int(members.size()) + add > k3.max_group_sides) continue;
+          best_new = add;
+          best = j;
+          if (add == 0) break;
+        }
+        if (best == n) break;
+        take(best);
+      }
+      for (int32_t x : members)
+        for (int32_t j : holders[x]) overlap[j] -= 1;
+      ends->push_back(out->size());
+      while (first < n && placed[first]) ++first;
+    }
+  };
+  // levels are clustered independently, on the host threads
+  std::vector<std::vector<PItem>> level_order(n_levels);
+  std::vector<std::vector<size_t>> level_ends(n_levels);
+  {
+    std::atomic<int> next_level{0};
+    std::vector<std::thread> workers;
+    for (int t = 0; t < std::min(n_threads, n_levels); ++t)
+      workers.emplace_back([&]() {
+        for (int L = next_level.fetch_add(1); L < n_levels; L = next_level.fetch_add(1))
+          cluster(level_items[L], &level_order[L], &level_ends[L]);
+      });
+    for (auto& w : workers) w.join();
+  }
   for (int L = n_levels - 1; L >= 0; --L) {
-    const auto& its = level_items[L];
+    const std::vector<PItem>& its = level_order[L];
+    const std::vector<size_t>& ends = level_ends[L];
     const int m = T.grid_sizes[L];
-    size_t g0 = 0;
+    size_t g0 = 0, gi = 0;
     while (g0 < its.size()) {
       std::vector<int32_t> gs;  // sorted, unique
       std::vector<uint32_t> b_used;
       size_t g1 = g0;
-      while (g1 < its.size() && g1 - g0 < size_t(kWavesPerGroup * ipw)) {
+      const size_t gend = ends[gi];
+      while (g1 < gend && g1 - g0 < size_t(kWavesPerGroup * ipw)) {
         std::vector<int32_t> add;
         uint32_t bu = 0;
         item_sides(its[g1], &add, &bu);
@@ -692,6 +766,7 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
       }
       T.max_group_sides = std::max(T.max_group_sides, zero_slot + 1);
       T.groups.push_back(gd);
+      if (g1 == gend) ++gi;
       g0 = g1;
     }
   }
