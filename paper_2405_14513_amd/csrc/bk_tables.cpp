@@ -440,8 +440,8 @@ std::string build_tables(const Binning& b, const K3Shape& k3, int n_threads, Tab
   // from the largest down; the free rows of an item are then filled with
   // segments of smaller grids that fit its window (a larger grid is still
   // exact).  Items of one grid are finally gathered into workgroups of up to
-  // kWavesPerGroup * items_per_wave across neighbouring plane triples while
-  // the staged sides stay within max_group_sides.
+  // kWavesPerGroup * items_per_wave items that share as many staged sides as
+  // a greedy clustering finds, within max_group_sides sides.
   const int n_levels = int(T.grid_sizes.size());
   struct Seg {
     int level, ra, rc, lo, hi;
