@@ -228,8 +228,9 @@ constexpr bool prec_is_f32() {
 }
 
 // LDS bytes of the contraction for a chunk of ch points (two buffers of every
-// staged slot plus the zero slot), 0 if the kernel has no instance for the
-// chunk (float32: 32 or 64 points, float64: 16 or 32), if it does not divide every grid
+// staged slot plus the zero slot; kK3FixedSlots slots each when the buffers
+// sit at a fixed stride), 0 if the kernel has no instance for the chunk
+// (float32: 32 or 64 points, float64: 16 or 32), if it does not divide every grid
 // level's m^2 points, gives fewer than 16 16-byte units per slot, needs more
 // staging lines than the kernel issues, or exceeds the 160 KiB of a CU.
 size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
@@ -242,6 +243,10 @@ size_t k3_lds_bytes(const bk::Tables& T, int prec, int ch) {
     if ((long(m) * m) % ch != 0) return 0;
   const size_t slot = size_t(ch) * cs;
   if (size_t(T.max_group_sides - 1) * slot > size_t(bk::kK3MaxLines) * bk::kWavesPerGroup * 1024) return 0;
+  // two items per wave with 256-byte slots: the kernel places its second
+  // buffer kK3FixedSlots slots after the first
+  if (T.k3.items_per_wave == 2 && slot == 256)
+    return T.max_group_sides <= bk::kK3FixedSlots ? 2 * size_t(bk::kK3FixedSlots) * slot : 0;
   const size_t lds = 2 * size_t(T.max_group_sides) * slot;
   return lds <= 163840 ? lds : 0;
 }

@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bk_fft.hpp"
 #include "bk_tables.hpp"
 
@@ -293,6 +295,8 @@ struct K3Stage {
 };
 constexpr int kK3Threads = 64 * kWavesPerGroup;
 constexpr int kK3MaxLines = 8;  // 1 KiB staging lines per wave per chunk
+// slots per staging buffer at a fixed buffer stride (159 sides and the zero slot)
+constexpr int kK3FixedSlots = 160;
 
 typedef double f64x2v __attribute__((ext_vector_type(2)));
 
@@ -342,7 +346,11 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
   const int kq = lane >> 4;
   const char* Db = reinterpret_cast<const char*>(D + size_t(b) * d_elems);
   const int nchunks = int((long(gd.grid) * gd.grid) / CH);  // m^2 is a multiple of CH
-  const int buf_bytes = (gd.n_sides + 1) * G::slot_bytes;
+  // With two items per wave and 256-byte slots the second buffer starts at a
+  // fixed offset (kK3FixedSlots slots), so that every operand read is a
+  // register plus an immediate offset; otherwise right after the first.
+  constexpr int kFixedStride = (IPW == 2 && G::slot_bytes == 256) ? kK3FixedSlots * 256 : 0;
+  const int buf_bytes = kFixedStride ? kFixedStride : (gd.n_sides + 1) * G::slot_bytes;
   const int data_bytes = gd.n_sides * G::slot_bytes;
 
   // the zero slot (last) of both buffers
@@ -432,14 +440,18 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
     for (int k = 0; k < 4; ++k) out_im[t][k] = 0.0;
   }
 
-  for (int c = 0; c < nchunks; ++c) {
+  // Chunk c sits in buffer sel; with a fixed buffer stride the loop is unrolled
+  // by two so that sel, and with it every LDS address offset, is a constant.
+  auto run_chunk = [&](int c, auto sel_c) {
+    constexpr int kSel = decltype(sel_c)::value;  // 0 or 1, or -1: c & 1 at run time
+    const int sel = kSel >= 0 ? kSel : (c & 1);
     // chunk c has landed (each wave waits for its own loads, the barrier for
     // everyone's) and every wave is done with the buffer chunk c + 1 will fill
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (c + 1 < nchunks) issue(c + 1, (c + 1) & 1);
+    if (c + 1 < nchunks) issue(c + 1, 1 - sel);
     if (active) {
-      const char* buf = smem_raw + (c & 1) * buf_bytes;
+      const char* buf = smem_raw + (kSel >= 0 ? kSel * kFixedStride : sel * buf_bytes);
       unit_t a_n[TILES], c_n[TILES], b_n[IPW];
       auto load_step = [&](int q, unit_t* a, unit_t* cc, unit_t* bv) {
         const int shift = 64 * q;
@@ -506,6 +518,14 @@ __global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* 
         }
       }
     }
+  };
+  if constexpr (kFixedStride > 0) {
+    for (int c = 0; c < nchunks; c += 2) {
+      run_chunk(c, std::integral_constant<int, 0>{});
+      if (c + 1 < nchunks) run_chunk(c + 1, std::integral_constant<int, 1>{});
+    }
+  } else {
+    for (int c = 0; c < nchunks; ++c) run_chunk(c, std::integral_constant<int, -1>{});
   }
   if constexpr (kFlush == 0) {
 #pragma unroll
