@@ -324,8 +324,13 @@ struct Unit<double> {
 // takes Re P Im D_B + Im P Re D_B = Im S); float32 units carry two points,
 // i.e. two k-steps.  Float32 partial sums are added to float64 registers
 // every 128 points; float64 accumulates in the MFMA registers.
+//
+// With two items per wave the Im S accumulators would take the kernel past
+// 128 VGPRs, leaving room for one block per CU; that instance is held to four
+// waves per SIMD (two blocks per CU) at the price of a few spilled registers.
 template <typename T, int CH, int TPI, int IPW, bool IMS>
-__global__ __launch_bounds__(kK3Threads) void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
+__global__ __launch_bounds__(kK3Threads) __attribute__((amdgpu_waves_per_eu(IMS && IPW == 2 && CH * 2 * sizeof(T) == 256 ? 4 : 1)))
+void k3_contract_kernel(const cplx<T>* __restrict__ D, long d_elems,
                                                                  const int64_t* __restrict__ gside_off,
                                                                  const GroupDesc* __restrict__ groups,
                                                                  const ItemDesc* __restrict__ items,
