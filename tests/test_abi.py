@@ -88,3 +88,27 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _random_binnings(n, seed=2405):
+    """Seeded binnings over small grids whose k1 edges often fall exactly on
+    ring edges (integers and thirds), to exercise the interval tie rules."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        ng = int(rng.choice([8, 16, 24, 32, 48]))
+        top = ng / 3.0
+        grid = np.arange(1, int(3 * top) + 1) / 3.0  # multiples of 1/3 up to N_g/3
+        k0, k1 = np.sort(rng.choice(grid, size=2, replace=False))
+        if rng.random() < 0.3 and k0 < top:
+            k1 = top
+        out.append((ng, int(rng.integers(1, 6)), float(k0), float(k1), int(rng.integers(1, 9)),
+                    int(rng.integers(1, 9))))
+    return out
+
+
+@pytest.mark.parametrize("args", _random_binnings(16))
+def test_host_triangle_counts_match_oracle_on_random_binnings(args):
+    counts, _ = bk.bk_count_triangles(bk.make_binning(*args))
+    g = make_geometry(Binning(*args))
+    assert np.array_equal(counts, g.bin_counts().reshape(counts.shape)), args
