@@ -102,8 +102,10 @@ typedef struct {
  * The contraction's work-item shape can be overridden the same way (results
  * equal up to rounding): BK_K3_PAIRS=32 or 64 (ring pairs per item, one item
  * per wave), BK_K3_ITEMS=1 or 2 (16-pair items per wave, default 2) and
- * BK_K3_SIDES (staged sides per workgroup, 1..254).  An invalid combination
- * fails with BK_ERR_ARG. */
+ * BK_K3_SIDES (staged sides per workgroup, 1..254; with two items per wave at
+ * most 159, since those workgroups stage into two fixed 160-slot buffers).
+ * An invalid combination, or one whose staging does not fit the LDS, fails
+ * with BK_ERR_ARG. */
 bk_status bk_plan_create(const bk_binning* binning, int prec, int device, int max_batch, bk_plan* out);
 
 /* A plan with several second-level binnings ("resolutions") of the same
